@@ -1,0 +1,104 @@
+"""CPU oracle for the LSD radix sort -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library in
+``paper_1511_03404_amd``) never loads it and shares no code with it.
+
+The arithmetic lives in ``lsd_oracle.c`` (plain C, compiled with gcc): a
+stable counting-sort LSD radix sort written from the paper's description
+(Section 2.6).  This module only marshals numpy arrays into it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lsd_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared",
+                               "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp, u64, ci = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+        lib.oracle_sort_u32.argtypes = [vp, vp, u64, ci, ci]
+        lib.oracle_sort_u64.argtypes = [vp, vp, u64, ci, ci]
+        lib.oracle_digit_histograms.argtypes = [vp, u64, ci, ci, vp]
+        lib.oracle_segmented_sort.argtypes = [ci, vp, vp, vp, u64, ci]
+        for f in (lib.oracle_sort_u32, lib.oracle_sort_u64, lib.oracle_digit_histograms,
+                  lib.oracle_segmented_sort):
+            f.restype = ci
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_pair(keys, vals):
+    keys = np.asarray(keys)
+    if keys.dtype not in (np.uint32, np.uint64):
+        raise TypeError("keys must be uint32 or uint64")
+    if vals is not None:
+        vals = np.asarray(vals)
+        if vals.dtype != keys.dtype or vals.shape != keys.shape:
+            raise TypeError("values must match the keys' dtype and length")
+    return keys, vals
+
+
+def sort(keys, vals=None, r: int = 8, passes: int = -1):
+    """Stable LSD sort by unsigned key.  Returns new arrays (keys, vals or None).
+
+    ``passes`` < 0 runs all ceil(K/r) passes; a smaller count returns the
+    state after that many counting-sort passes."""
+    keys, vals = _check_pair(keys, vals)
+    k = np.array(keys, copy=True, order="C")
+    v = None if vals is None else np.array(vals, copy=True, order="C")
+    f = _load().oracle_sort_u32 if k.dtype == np.uint32 else _load().oracle_sort_u64
+    if f(_ptr(k), _ptr(v), k.size, r, passes) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return k, v
+
+
+def digit_histograms(keys, r: int = 8) -> np.ndarray:
+    """hist[p, b] = number of input keys whose digit p equals b."""
+    keys = np.ascontiguousarray(keys)
+    bits = 32 if keys.dtype == np.uint32 else 64
+    d = (bits + r - 1) // r
+    h = np.zeros((d, 1 << r), dtype=np.uint64)
+    if _load().oracle_digit_histograms(_ptr(keys), keys.size, bits, r, _ptr(h)) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return h
+
+
+def segmented_sort(keys, vals, offsets, r: int = 8):
+    """Sort each segment [offsets[s], offsets[s+1]) on its own."""
+    keys, vals = _check_pair(keys, vals)
+    k = np.array(keys, copy=True, order="C")
+    v = None if vals is None else np.array(vals, copy=True, order="C")
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    bits = 32 if k.dtype == np.uint32 else 64
+    if off.size < 1 or int(off[-1]) > k.size:
+        raise ValueError("offsets out of range")
+    if _load().oracle_segmented_sort(bits, _ptr(k), _ptr(v), _ptr(off), off.size - 1, r) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return k, v
