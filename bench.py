@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 LSD radix sort.
+
+Default workload: one step sorts 2^26 (32-bit key, 32-bit value) pairs
+(value = input index) once on each of the six input distributions (uniform,
+gaussian, zero, sorted, reverse, bucket; MT19937 seed 1), inputs resident in
+HBM before timing starts, out-of-place so every step sorts the same input.
+Reported: whole-job Mkeys/s, the HBM roofline of the dominant kernel (the
+digit pass) measured with HIP events on the library's launch stream, and the
+CPU oracle's rate on a bounded sample.
+
+Other workloads (``--workload``): u64_keys / u64_pairs (2^25 64-bit), and
+u32_keys_small (2^20 32-bit keys).  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    # name: (n, key bits, has values, description)
+    "u32_pairs": (1 << 26, 32, True, "2^26 u32 key + u32 value pairs (value = input index)"),
+    "u64_keys": (1 << 25, 64, False, "2^25 u64 keys, full 64-bit range"),
+    "u64_pairs": (1 << 25, 64, True, "2^25 u64 key + u64 value pairs (value = input index)"),
+    "u32_keys_small": (1 << 20, 32, False, "2^20 u32 keys (latency-bound, cache-resident)"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="u32_pairs", choices=sorted(WORKLOADS))
+    ap.add_argument("--dists", default="all",
+                    help="comma list of distributions, or 'all' for the six")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    return ap.parse_args()
+
+
+def cpu_baseline(bits, has_v, dists, sample_log2):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    one sort per distribution at n = 2^sample_log2 (single thread)."""
+    import datagen
+    import oracle
+    n = 1 << sample_log2
+    total_t = 0.0
+    for d in dists:
+        k = datagen.keys(d, n, bits, seed=1)
+        v = datagen.values(n, bits) if has_v else None
+        t0 = time.perf_counter()
+        oracle.sort(k, v)
+        total_t += time.perf_counter() - t0
+    return {
+        "value": round(len(dists) * n / total_t / 1e6, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one sort per distribution ({','.join(dists)}) at n=2^{sample_log2}, "
+                  f"{bits}-bit {'pairs' if has_v else 'keys'}, seed 1; {total_t:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                          "a design note, not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import datagen
+    import paper_1511_03404_amd as rs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    rs.lib()  # fails loudly if librs.so is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, bits, has_v, wdesc = WORKLOADS[args.workload]
+    dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")
+    kb = bits // 8
+    vb = kb if has_v else 0
+
+    # inputs resident in HBM before timing
+    ins = []
+    for d in dists:
+        k = torch.from_numpy(datagen.keys(d, n, bits, seed=1)).to(dev)
+        v = torch.from_numpy(datagen.values(n, bits)).to(dev) if has_v else None
+        ins.append((d, k, v))
+    ko = torch.empty(n, dtype=ins[0][1].dtype, device=dev)
+    vo = torch.empty(n, dtype=ins[0][1].dtype, device=dev) if has_v else None
+    ctx = rs.context(0)
+    ws = torch.empty(ctx.workspace_bytes(bits, has_v, n), dtype=torch.uint8, device=dev)
+
+    def step():
+        for i, (d, k, v) in enumerate(ins):
+            ctx.profile_tag(i)
+            if has_v:
+                rs.sort_pairs(k, v, ko, vo, ctx=ctx, workspace=ws)
+            else:
+                rs.sort_keys(k, ko, ctx=ctx, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.profile_enable(False)
+    recs = ctx.profile_read()
+
+    elapsed = t1 - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    keys_total = n * len(dists) * args.steps
+    value = keys_total / elapsed / 1e6
+
+    # per-distribution times from the events (sum of the kernels of one sort)
+    per = {}
+    for i, d in enumerate(dists):
+        tot = sum(ms for name, tag, ms in recs if tag == i)
+        sort_ms = tot / args.steps
+        b_alg = kb * 2 * n * (kb + vb)  # P8 passes x 2 x n x (k + v)
+        per[d] = {"ms_per_sort": round(sort_ms, 4),
+                  "Mkeys_s": round(n / sort_ms / 1e3, 1),
+                  "hbm_frac_alg": round(b_alg / (sort_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        kern = {}
+        for name, tag, ms in recs:
+            if tag == i:
+                kern.setdefault(name, []).append(ms)
+        per[d]["kernels_ms"] = {k: round(sum(v) / args.steps, 4) for k, v in kern.items()}
+
+    # roofline of the dominant kernel: the digit pass, on the input where
+    # every pass moves data (uniform), per launch
+    pass_name = f"k_pass_u{bits}_{'pairs' if has_v else 'keys'}"
+    ref = dists.index("uniform") if "uniform" in dists else 0
+    pass_ms = [ms for name, tag, ms in recs if tag == ref and name == pass_name]
+    roofline = None
+    if pass_ms:
+        avg = sum(pass_ms) / len(pass_ms)
+        bytes_per_launch = 2 * n * (kb + vb)  # read + write of keys and values, one digit
+        achieved = bytes_per_launch / (avg * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": pass_name, "avg_launch_ms": round(avg, 5),
+                    "launches": len(pass_ms), "bytes_per_launch": bytes_per_launch,
+                    "input": dists[ref]}
+
+    whole_frac = (kb * 2 * n * (kb + vb)) * len(dists) * args.steps / elapsed / (HBM_PEAK_GBS * 1e9)
+    out = {
+        "metric": "Mkeys/s and % HBM roofline",
+        "value": round(value, 1),
+        "unit": "Mkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": f"u{bits}",
+        "data": "synthetic",
+        "config": {"workload": f"{wdesc}; one sort per distribution per step "
+                               f"({', '.join(dists)}); MT19937 seed 1",
+                   "n": n, "key_bits": bits, "value_bits": bits if has_v else 0,
+                   "distributions": dists, "digit_bits": 8},
+        "hbm_frac_whole_sort": round(whole_frac, 4),
+        "roofline": roofline,
+        "per_distribution": per,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(bits, has_v, dists, args.cpu_sample_log2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

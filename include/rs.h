@@ -1,0 +1,167 @@
+/*
+ * rs.h -- C-ABI of the MI355X (gfx950) LSD radix sort library (librs.so).
+ *
+ * The operation is the least-significant-digit radix sort described in the
+ * paper (Bozidar & Dobravec, "Comparison of parallel sorting algorithms",
+ * Section 2.6): keys are split into r-bit digits and sorted digit by digit
+ * from the least significant one, each pass being a stable counting sort.
+ * Inputs are 32-bit or 64-bit unsigned keys, alone or with a value of the
+ * same width (Sections 1 and 3), of any length (Section 1).  The result is
+ * the ascending, stable sort by unsigned key: equal keys keep their input
+ * order, and each value travels with its key.  Exactly one output is
+ * correct, so results are bit-exact.
+ *
+ * Conventions shared by every entry point below:
+ *
+ *  - Pointers named *_in, *_out, ws and offsets are DEVICE pointers on the
+ *    context's device (hipMalloc / torch allocations).  Keys and values are
+ *    separate arrays (structure of arrays).  Alignment: 4 bytes for 32-bit
+ *    data, 8 bytes for 64-bit data.
+ *  - The caller owns every buffer.  The library never frees what it did not
+ *    allocate.
+ *  - *_out may equal *_in (in-place).  Any other overlap between an input
+ *    and an output, or between keys and values, is RS_ERR_INVALID_ARGUMENT.
+ *  - ws / ws_bytes: scratch memory of at least rs_workspace_bytes() bytes,
+ *    256-byte aligned.  ws == NULL makes the context allocate and keep a
+ *    scratch buffer of its own (grow-only, freed by rs_context_destroy);
+ *    that mode calls hipMalloc and is therefore not usable under stream
+ *    capture.
+ *  - stream is a hipStream_t (NULL = the device's null stream).  Calls are
+ *    asynchronous: the output is valid once the stream has completed.
+ *    Device faults surface at the caller's next synchronisation.
+ *  - Arguments are validated on the host before any HIP call; a rejected
+ *    call enqueues nothing.  n = 0 is valid and enqueues nothing.
+ *  - One sort handles n < 2^30 elements (RS_ERR_UNSUPPORTED above that).
+ *  - Nothing is thrown across this interface.  rs_last_error() returns a
+ *    thread-local description of the last failure.
+ *  - A context may be used from one host thread at a time.
+ */
+#ifndef RS_H
+#define RS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rs_status {
+    RS_OK = 0,
+    RS_ERR_INVALID_ARGUMENT = 1, /* bad pointer, size, alignment, overlap, workspace */
+    RS_ERR_UNSUPPORTED = 2,      /* valid request outside this version's limits */
+    RS_ERR_OUT_OF_MEMORY = 3,    /* the context could not allocate its own scratch */
+    RS_ERR_DEVICE = 4            /* a HIP call failed (launch, device selection) */
+} rs_status;
+
+typedef enum rs_key_type {
+    RS_KEY_U32 = 0,
+    RS_KEY_U64 = 1
+} rs_key_type;
+
+typedef struct rs_context rs_context; /* opaque */
+
+/* Maximum elements in one sort or one segmented batch. */
+#define RS_MAX_ELEMENTS ((uint64_t)1 << 30)
+
+/*
+ * Create a context bound to HIP device `device`.  HIP is touched lazily: the
+ * device is only selected when the first sort is enqueued, so a context can
+ * be created (and arguments validated) on a machine without a GPU.
+ * *out receives the context; release it with rs_context_destroy.
+ */
+rs_status rs_context_create(int device, rs_context **out);
+
+/* Release a context and any scratch memory it allocated.  NULL is a no-op. */
+void rs_context_destroy(rs_context *ctx);
+
+/*
+ * Bytes of scratch memory one sort of n elements needs (look-back words,
+ * digit histograms, one ping-pong copy of the keys and values).  Pure host
+ * arithmetic; never touches the device.
+ */
+rs_status rs_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int has_values,
+                             uint64_t n, size_t *bytes);
+
+/*
+ * Stable ascending sort of n 32-bit keys (Section 2.6): keys_out receives the
+ * keys of keys_in in ascending unsigned order.  keys_in is read, never
+ * written, unless keys_out == keys_in.
+ */
+rs_status rs_sort_keys_u32(rs_context *ctx, const uint32_t *keys_in, uint32_t *keys_out,
+                           uint64_t n, void *ws, size_t ws_bytes, void *stream);
+
+/* As rs_sort_keys_u32 for 64-bit keys (8 digit passes of 8 bits). */
+rs_status rs_sort_keys_u64(rs_context *ctx, const uint64_t *keys_in, uint64_t *keys_out,
+                           uint64_t n, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Stable sort of n (32-bit key, 32-bit value) pairs by key (Sections 1, 2.6):
+ * output position i holds the pair with the i-th smallest (key, input index).
+ */
+rs_status rs_sort_pairs_u32(rs_context *ctx, const uint32_t *keys_in, const uint32_t *vals_in,
+                            uint32_t *keys_out, uint32_t *vals_out, uint64_t n, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* As rs_sort_pairs_u32 for 64-bit keys with 64-bit values. */
+rs_status rs_sort_pairs_u64(rs_context *ctx, const uint64_t *keys_in, const uint64_t *vals_in,
+                            uint64_t *keys_out, uint64_t *vals_out, uint64_t n, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/*
+ * Batched segmented sort: num_segments independent stable sorts, segment s
+ * being elements [offsets[s], offsets[s+1]) of the arrays, sorted within its
+ * own range.  offsets is a DEVICE array of num_segments+1 uint64 values,
+ * non-decreasing, offsets[0] >= 0 and offsets[num_segments] <= total; empty
+ * segments are allowed.  vals_in/vals_out NULL = keys only.  Elements outside
+ * every segment are left untouched in *_out.  Bytes of scratch:
+ * rs_segmented_workspace_bytes().  Offsets are read on the device only (no
+ * host round trip); a non-monotone offsets array is not detected and gives
+ * unspecified (but in-bounds) results.
+ */
+rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *keys_in,
+                            const void *vals_in, void *keys_out, void *vals_out,
+                            const uint64_t *offsets, uint32_t num_segments, uint64_t total,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Scratch bytes for rs_segmented_sort on `total` elements in num_segments
+ * segments.  Pure host arithmetic. */
+rs_status rs_segmented_workspace_bytes(const rs_context *ctx, rs_key_type key_type,
+                                       int has_values, uint64_t total, uint32_t num_segments,
+                                       size_t *bytes);
+
+/*
+ * Per-kernel timing for benchmarks and profiling.  While enabled, every
+ * kernel the context launches is bracketed by two HIP events recorded on the
+ * launch stream, and the pair is kept with the kernel's name and the tag set
+ * by rs_profile_tag().  Disabled by default; enabling costs two event
+ * records per launch and no synchronisation.
+ */
+rs_status rs_profile_enable(rs_context *ctx, int enable);
+
+/* Tag attached to the records of later launches (e.g. an input id). */
+rs_status rs_profile_tag(rs_context *ctx, int tag);
+
+/* Drop all records. */
+rs_status rs_profile_reset(rs_context *ctx);
+
+/*
+ * Synchronise on the recorded events and copy out up to `max` records:
+ * names[i] points to a static kernel name, tags[i] is the tag, ms[i] the
+ * elapsed time between the record's two events in milliseconds.  *count
+ * receives the number of records held (which may exceed max).
+ */
+rs_status rs_profile_read(rs_context *ctx, const char **names, int *tags, float *ms, int max,
+                          int *count);
+
+/* Static description of a status code. */
+const char *rs_status_string(rs_status status);
+
+/* Thread-local detail of the last failed call on this thread ("" if none). */
+const char *rs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_H */

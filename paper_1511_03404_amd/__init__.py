@@ -1,0 +1,275 @@
+"""MI355X (gfx950) LSD radix sort: Python binding of ``librs.so``.
+
+The binding only marshals arguments: every step of the sort runs in the HIP
+kernels of ``csrc/``.  PyTorch supplies device memory and the current stream.
+If the library has not been built, every call raises; there is no CPU path.
+
+Keys are unsigned.  A 32-bit sort takes ``torch.uint32`` or ``torch.int32``
+tensors, a 64-bit sort ``torch.uint64`` or ``torch.int64``; signed tensors
+are sorted by their bit pattern read as unsigned.  Values have the key's
+width.  All sorts are stable and ascending (paper, Section 2.6).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librs.so")
+
+RS_OK = 0
+RS_ERR_INVALID_ARGUMENT = 1
+RS_ERR_UNSUPPORTED = 2
+RS_ERR_OUT_OF_MEMORY = 3
+RS_ERR_DEVICE = 4
+RS_KEY_U32 = 0
+RS_KEY_U64 = 1
+MAX_ELEMENTS = 1 << 30
+
+EXPORTED = (
+    "rs_context_create", "rs_context_destroy", "rs_workspace_bytes",
+    "rs_sort_keys_u32", "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
+    "rs_segmented_sort", "rs_segmented_workspace_bytes", "rs_status_string", "rs_last_error",
+    "rs_profile_enable", "rs_profile_tag", "rs_profile_reset", "rs_profile_read",
+)
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+class RSError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"rs status {status}: {message}")
+        self.status = status
+
+
+def lib():
+    """The loaded ``librs.so``; raises if it has not been built."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "librs.so is not built; run `python -m paper_1511_03404_amd.build` "
+                    "(there is no CPU fallback)")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, u64, u32, ci = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+            sz = ctypes.c_size_t
+            L.rs_context_create.argtypes = [ci, ctypes.POINTER(vp)]
+            L.rs_context_destroy.argtypes = [vp]
+            L.rs_context_destroy.restype = None
+            L.rs_workspace_bytes.argtypes = [vp, ci, ci, u64, ctypes.POINTER(sz)]
+            L.rs_sort_keys_u32.argtypes = [vp, vp, vp, u64, vp, sz, vp]
+            L.rs_sort_keys_u64.argtypes = [vp, vp, vp, u64, vp, sz, vp]
+            L.rs_sort_pairs_u32.argtypes = [vp, vp, vp, vp, vp, u64, vp, sz, vp]
+            L.rs_sort_pairs_u64.argtypes = [vp, vp, vp, vp, vp, u64, vp, sz, vp]
+            L.rs_segmented_sort.argtypes = [vp, ci, vp, vp, vp, vp, vp, u32, u64, vp, sz, vp]
+            L.rs_segmented_workspace_bytes.argtypes = [vp, ci, ci, u64, u32, ctypes.POINTER(sz)]
+            L.rs_status_string.argtypes = [ci]
+            L.rs_status_string.restype = ctypes.c_char_p
+            L.rs_profile_enable.argtypes = [vp, ci]
+            L.rs_profile_tag.argtypes = [vp, ci]
+            L.rs_profile_reset.argtypes = [vp]
+            L.rs_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p),
+                                          ctypes.POINTER(ci), ctypes.POINTER(ctypes.c_float),
+                                          ci, ctypes.POINTER(ci)]
+            L.rs_last_error.argtypes = []
+            L.rs_last_error.restype = ctypes.c_char_p
+            for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
+                         "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
+                         "rs_segmented_sort", "rs_segmented_workspace_bytes",
+                         "rs_profile_enable", "rs_profile_tag", "rs_profile_reset",
+                         "rs_profile_read"):
+                getattr(L, name).restype = ci
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != RS_OK:
+        msg = lib().rs_last_error().decode(errors="replace")
+        raise RSError(status, msg)
+
+
+class Context:
+    """An ``rs_context`` bound to one HIP device."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device() if torch.cuda.is_available() else 0
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check(lib().rs_context_create(self.device, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().rs_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, key_bits: int, has_values: bool, n: int) -> int:
+        out = ctypes.c_size_t()
+        kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
+        _check(lib().rs_workspace_bytes(self.handle, kt, int(has_values), n, ctypes.byref(out)))
+        return out.value
+
+    def segmented_workspace_bytes(self, key_bits: int, has_values: bool, total: int,
+                                  num_segments: int) -> int:
+        out = ctypes.c_size_t()
+        kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
+        _check(lib().rs_segmented_workspace_bytes(self.handle, kt, int(has_values), total,
+                                                  num_segments, ctypes.byref(out)))
+        return out.value
+
+
+    # -- per-kernel timing (HIP events around each launch) ---------------
+    def profile_enable(self, on: bool = True):
+        _check(lib().rs_profile_enable(self.handle, int(on)))
+
+    def profile_tag(self, tag: int):
+        _check(lib().rs_profile_tag(self.handle, int(tag)))
+
+    def profile_reset(self):
+        _check(lib().rs_profile_reset(self.handle))
+
+    def profile_read(self):
+        """List of (kernel name, tag, milliseconds); synchronises."""
+        count = ctypes.c_int()
+        _check(lib().rs_profile_read(self.handle, None, None, None, 0, ctypes.byref(count)))
+        m = count.value
+        if m == 0:
+            return []
+        names = (ctypes.c_char_p * m)()
+        tags = (ctypes.c_int * m)()
+        ms = (ctypes.c_float * m)()
+        _check(lib().rs_profile_read(self.handle, names, tags, ms, m, ctypes.byref(count)))
+        return [(names[i].decode(), tags[i], ms[i]) for i in range(m)]
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    """Process-wide default context of a device."""
+    if device is None:
+        device = torch.cuda.current_device()
+    c = _contexts.get(device)
+    if c is None:
+        c = _contexts[device] = Context(device)
+    return c
+
+
+_BITS = {torch.uint32: 32, torch.int32: 32, torch.uint64: 64, torch.int64: 64}
+
+
+def key_bits(t: torch.Tensor) -> int:
+    b = _BITS.get(t.dtype)
+    if b is None:
+        raise TypeError(f"unsupported key dtype {t.dtype}; use (u)int32 or (u)int64")
+    return b
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device: int):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(t: torch.Tensor, name: str, bits: int, n: int):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if key_bits(t) != bits:
+        raise TypeError(f"{name} must have the keys' width ({bits} bits)")
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with {n} elements")
+
+
+def _workspace(ctx: Context, nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def sort_keys(keys: torch.Tensor, out: torch.Tensor | None = None, *, ctx: Context | None = None,
+              workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Ascending stable sort of a 1-D key tensor.  ``out`` may be ``keys``
+    (in place).  Asynchronous on the current stream."""
+    bits = key_bits(keys)
+    n = keys.numel()
+    _check_tensor(keys, "keys", bits, n)
+    if out is None:
+        out = torch.empty_like(keys)
+    _check_tensor(out, "out", bits, n)
+    ctx = ctx or context(keys.device.index)
+    if n == 0:
+        return out
+    need = ctx.workspace_bytes(bits, False, n)
+    ws = workspace if workspace is not None else _workspace(ctx, need, keys.device)
+    f = lib().rs_sort_keys_u32 if bits == 32 else lib().rs_sort_keys_u64
+    _check(f(ctx.handle, _ptr(keys), _ptr(out), n, _ptr(ws), ws.numel(), _stream(ctx.device)))
+    return out
+
+
+def sort_pairs(keys: torch.Tensor, values: torch.Tensor, keys_out: torch.Tensor | None = None,
+               values_out: torch.Tensor | None = None, *, ctx: Context | None = None,
+               workspace: torch.Tensor | None = None):
+    """Stable sort of (key, value) pairs by key.  Returns (keys_out, values_out)."""
+    bits = key_bits(keys)
+    n = keys.numel()
+    _check_tensor(keys, "keys", bits, n)
+    _check_tensor(values, "values", bits, n)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    values_out = torch.empty_like(values) if values_out is None else values_out
+    _check_tensor(keys_out, "keys_out", bits, n)
+    _check_tensor(values_out, "values_out", bits, n)
+    ctx = ctx or context(keys.device.index)
+    if n == 0:
+        return keys_out, values_out
+    need = ctx.workspace_bytes(bits, True, n)
+    ws = workspace if workspace is not None else _workspace(ctx, need, keys.device)
+    f = lib().rs_sort_pairs_u32 if bits == 32 else lib().rs_sort_pairs_u64
+    _check(f(ctx.handle, _ptr(keys), _ptr(values), _ptr(keys_out), _ptr(values_out), n,
+             _ptr(ws), ws.numel(), _stream(ctx.device)))
+    return keys_out, values_out
+
+
+def segmented_sort(keys: torch.Tensor, values: torch.Tensor | None, offsets: torch.Tensor,
+                   keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
+                   *, ctx: Context | None = None, workspace: torch.Tensor | None = None):
+    """Sort every segment [offsets[s], offsets[s+1]) on its own, in one batch.
+    ``offsets`` is a device int64/uint64 tensor of num_segments + 1 entries."""
+    bits = key_bits(keys)
+    n = keys.numel()
+    _check_tensor(keys, "keys", bits, n)
+    has_v = values is not None
+    if has_v:
+        _check_tensor(values, "values", bits, n)
+    if offsets.dtype not in (torch.int64, torch.uint64) or not offsets.is_cuda \
+            or not offsets.is_contiguous() or offsets.numel() < 1:
+        raise ValueError("offsets must be a contiguous device int64 tensor of S+1 entries")
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    _check_tensor(keys_out, "keys_out", bits, n)
+    if has_v:
+        values_out = torch.empty_like(values) if values_out is None else values_out
+        _check_tensor(values_out, "values_out", bits, n)
+    else:
+        values_out = None
+    ctx = ctx or context(keys.device.index)
+    nseg = offsets.numel() - 1
+    kt = RS_KEY_U32 if bits == 32 else RS_KEY_U64
+    need = ctx.segmented_workspace_bytes(bits, has_v, n, nseg)
+    ws = workspace if workspace is not None else _workspace(ctx, need, keys.device)
+    _check(lib().rs_segmented_sort(ctx.handle, kt, _ptr(keys), _ptr(values), _ptr(keys_out),
+                                   _ptr(values_out), _ptr(offsets), nseg, n, _ptr(ws),
+                                   ws.numel(), _stream(ctx.device)))
+    return keys_out, values_out
+

@@ -1,0 +1,142 @@
+// Device building blocks of the gfx950 LSD radix sort.
+//
+// One digit pass is the stable counting sort of the paper's radix sort
+// (Section 2.6): count the digits, exclusive-scan the counts, place every
+// element at its digit's running offset in input order.  On the GPU the
+// three steps are spread over a tile of T elements per workgroup:
+//   * count  -- a wave64 "multisplit": eight ballots give each lane the mask
+//               of lanes holding the same digit; the lowest such lane adds
+//               the group size to a per-wave LDS counter, and the rank inside
+//               the group is mbcnt over the mask.  Items are visited in input
+//               order (wave-striped: item j of lane l is element j*64 + l of
+//               the wave's run), which is what makes the ranking stable;
+//   * scan   -- digit_base (global exclusive scan of the digit histogram) +
+//               a decoupled look-back over the tiles before this one +
+//               the tile-local exclusive scan over digits and waves;
+//   * place  -- stage the tile in LDS in rank order, then write each digit
+//               run out with consecutive lanes on consecutive addresses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kWave = 64;
+
+// Look-back status word: [31:30] flag, [29:0] digit count.
+constexpr uint32_t kFlagAgg = 1u << 30;  // count of this tile only
+constexpr uint32_t kFlagInc = 2u << 30;  // count of all tiles up to and including this one
+constexpr uint32_t kFlagMask = 3u << 30;
+constexpr uint32_t kCountMask = (1u << 30) - 1;
+
+// Control block (u32 words at the start of the workspace).
+constexpr int kCtrlTileCounter = 0;  // [0, 8): dynamic tile id per pass
+constexpr int kCtrlHistDone = 8;     // workgroups of the histogram kernel that finished
+constexpr int kCtrlPlan = 16;        // [16, 24): plan word per pass
+constexpr int kCtrlFinal = 32;       // final copy: 0 none, 1 tmp -> out
+constexpr int kCtrlWords = 64;
+
+// Plan word of one pass.
+constexpr uint32_t kPlanRun = 1u;          // the pass moves data
+constexpr uint32_t kPlanCopyIn = 2u;       // no pass runs: copy in -> out here
+constexpr int kPlanSrcShift = 2;           // buffer id, 2 bits
+constexpr int kPlanDstShift = 4;           // buffer id, 2 bits
+constexpr uint32_t kBufIn = 0, kBufOut = 1, kBufTmp = 2;
+
+template <typename K>
+struct KeyTraits;
+
+template <>
+struct KeyTraits<uint32_t> {
+    static constexpr int kBits = 32;
+    static constexpr uint32_t kPad = 0xFFFFFFFFu;
+    __device__ static __forceinline__ uint32_t digit(uint32_t k, int shift)
+    {
+        return __builtin_amdgcn_ubfe(k, (uint32_t)shift, (uint32_t)kRadixBits);
+    }
+};
+
+template <>
+struct KeyTraits<uint64_t> {
+    static constexpr int kBits = 64;
+    static constexpr uint64_t kPad = ~0ull;
+    __device__ static __forceinline__ uint32_t digit(uint64_t k, int shift)
+    {
+        uint32_t w = shift < 32 ? (uint32_t)k : (uint32_t)(k >> 32);
+        return __builtin_amdgcn_ubfe(w, (uint32_t)(shift & 31), (uint32_t)kRadixBits);
+    }
+};
+
+__device__ __forceinline__ uint32_t lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Mask of the lanes of this (full) wave whose 8-bit digit equals ours.
+__device__ __forceinline__ uint64_t peer_mask(uint32_t d)
+{
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t s = __ballot(bit);
+        m &= bit ? s : ~s;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t shfl_idx(uint32_t v, uint32_t src_lane)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src_lane << 2), (int)v);
+}
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t o = shfl_idx(v, lane >= (uint32_t)off ? lane - off : lane);
+        if (lane >= (uint32_t)off)
+            v += o;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over the first 256 threads of the
+// block (4 waves).  `tmp` is 4 words of LDS.  Must be called by every thread
+// of the block (barriers inside); threads >= 256 get 0.
+template <int THREADS>
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *tmp)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t / kWave;
+    uint32_t inc = 0;
+    if (t < kRadix) {
+        inc = wave_inclusive_scan(v);
+        if ((t & (kWave - 1)) == kWave - 1)
+            tmp[w] = inc;
+    }
+    __syncthreads();
+    uint32_t excl = 0;
+    if (t < kRadix) {
+        uint32_t before = 0;
+        for (uint32_t i = 0; i < w; ++i)
+            before += tmp[i];
+        excl = before + inc - v;
+    }
+    __syncthreads();
+    return excl;
+}
+
+}  // namespace rs

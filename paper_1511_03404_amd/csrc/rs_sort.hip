@@ -1,0 +1,849 @@
+// LSD radix sort for gfx950 (MI355X) behind the C-ABI declared in rs.h.
+//
+// Method (paper, Section 2.6): d = K/8 passes of 8-bit digits, least
+// significant first, each a stable counting sort.  The GPU realisation:
+//
+//   k_init     zero the control block and the digit histograms
+//   k_hist     one read of the keys -> histograms of all d digit positions;
+//              the last workgroup to finish scans each row into digit_base
+//              (the counting sort's exclusive prefix sums) and writes a plan:
+//              which passes move data (a pass whose histogram has a single
+//              non-empty digit is the identity and is skipped) and which
+//              buffer each pass reads and writes.  It also clears the
+//              look-back words of every pass.
+//   k_pass     one per digit position: a single sweep over the data that
+//              counts, scans (decoupled look-back across tiles) and places
+//              each tile; see rs_device.h.
+//   k_finalize in-place sorts with an odd number of moving passes only:
+//              copy the scratch copy back.
+//
+// Everything after argument validation is enqueued on the caller's stream
+// with no host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rs.h"
+#include "rs_device.h"
+
+namespace rs {
+
+// ---------------------------------------------------------------------------
+// Tile shapes.
+
+template <typename K, bool HAS_V>
+struct PassShape {
+    static constexpr int kThreads = 256;
+    static constexpr int kItems = 16;
+    static constexpr int kTile = kThreads * kItems;
+};
+
+constexpr int kHistThreads = 256;
+
+struct Bufs {
+    const void *in_k;
+    const void *in_v;
+    void *out_k;
+    void *out_v;
+    void *tmp_k;
+    void *tmp_v;
+};
+
+template <typename T>
+__device__ __forceinline__ T *pick(const Bufs &b, uint32_t id, bool values)
+{
+    const void *p = values ? (id == kBufIn ? b.in_v : id == kBufOut ? b.out_v : b.tmp_v)
+                           : (id == kBufIn ? b.in_k : id == kBufOut ? b.out_k : b.tmp_k);
+    return (T *)p;
+}
+
+// ---------------------------------------------------------------------------
+// k_init: clear the control block and the histograms.
+
+__global__ void k_init(uint32_t *ctrl, uint32_t *hist, int hist_words)
+{
+    for (int i = threadIdx.x; i < kCtrlWords; i += blockDim.x)
+        ctrl[i] = 0;
+    for (int i = threadIdx.x; i < hist_words; i += blockDim.x)
+        hist[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_hist: all-digit histograms in one read, then (last workgroup) the scans
+// and the pass plan.
+
+struct HistArgs {
+    const void *keys;
+    uint32_t n;
+    uint32_t head;        // leading keys before the first 16-byte boundary
+    uint32_t nvec;        // 16-byte vectors after the head
+    uint32_t *hist;       // [d][256]
+    uint32_t *digit_base; // [d][256]
+    uint32_t *ctrl;
+    uint4 *status;        // look-back words of all passes, cleared here
+    uint64_t status_vec;  // number of uint4 in status
+    int in_place;
+};
+
+template <typename K>
+__device__ __forceinline__ void count_key(uint32_t (*sh)[kRadix], K key, uint32_t lane)
+{
+    constexpr int D = KeyTraits<K>::kBits / kRadixBits;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+        const uint32_t dg = KeyTraits<K>::digit(key, p * kRadixBits);
+        const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
+        const uint64_t same = __ballot(dg == first);
+        const uint64_t active = __ballot(1);
+        if (same == active) {  // wave-uniform digit: one update for the wave
+            if (lanes_below(active) == 0)
+                atomicAdd(&sh[p][dg], (uint32_t)__popcll(active));
+        } else {
+            atomicAdd(&sh[p][dg], 1u);
+        }
+    }
+    (void)lane;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
+{
+    constexpr int D = KeyTraits<K>::kBits / kRadixBits;
+    constexpr int W = kHistThreads / kWave;
+    constexpr int KPV = 16 / (int)sizeof(K);
+    __shared__ uint32_t sh[W][D][kRadix];
+    __shared__ uint32_t s_tmp[8];
+    __shared__ int s_last;
+    __shared__ int s_trivial[D];
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t / kWave;
+    const uint32_t lane = t % kWave;
+    for (int i = t; i < W * D * kRadix; i += kHistThreads)
+        (&sh[0][0][0])[i] = 0;
+
+    // clear the look-back words of every pass
+    const uint64_t gtid = (uint64_t)blockIdx.x * kHistThreads + t;
+    const uint64_t gstride = (uint64_t)gridDim.x * kHistThreads;
+    for (uint64_t i = gtid; i < a.status_vec; i += gstride)
+        a.status[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+
+    const K *keys = (const K *)a.keys;
+    const uint4 *vec = (const uint4 *)(keys + a.head);
+    for (uint64_t i = gtid; i < a.nvec; i += gstride) {
+        const uint4 v = vec[i];
+        if constexpr (KPV == 4) {
+            count_key<K>(sh[w], (K)v.x, lane);
+            count_key<K>(sh[w], (K)v.y, lane);
+            count_key<K>(sh[w], (K)v.z, lane);
+            count_key<K>(sh[w], (K)v.w, lane);
+        } else {
+            count_key<K>(sh[w], (K)(((uint64_t)v.y << 32) | v.x), lane);
+            count_key<K>(sh[w], (K)(((uint64_t)v.w << 32) | v.z), lane);
+        }
+    }
+    // unaligned head and ragged tail, element by element
+    const uint64_t tail0 = (uint64_t)a.head + (uint64_t)a.nvec * KPV;
+    const uint64_t extra = a.head + (a.n - tail0);
+    for (uint64_t i = gtid; i < extra; i += gstride) {
+        const uint64_t idx = i < a.head ? i : tail0 + (i - a.head);
+        count_key<K>(sh[w], keys[idx], lane);
+    }
+    __syncthreads();
+
+    for (int i = t; i < D * kRadix; i += kHistThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww)
+            s += (&sh[ww][0][0])[i];
+        if (s)
+            atomicAdd(&a.hist[i], s);
+    }
+
+    // last workgroup: scans and plan
+    __threadfence();
+    __syncthreads();
+    if (t == 0)
+        s_last = atomicAdd(&a.ctrl[kCtrlHistDone], 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last)
+        return;
+    __threadfence();
+    for (int p = 0; p < D; ++p) {
+        const uint32_t c = __hip_atomic_load(&a.hist[p * kRadix + t], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t ex = block_exclusive_scan_256<kHistThreads>(c, s_tmp);
+        a.digit_base[p * kRadix + t] = ex;
+        const int triv = __syncthreads_or(c == a.n);
+        if (t == 0)
+            s_trivial[p] = triv;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int q_total = 0;
+        for (int p = 0; p < D; ++p)
+            q_total += !s_trivial[p];
+        const bool odd_in_place = a.in_place && (q_total & 1);
+        int q = 0;
+        uint32_t prev = kBufIn;
+        for (int p = 0; p < D; ++p) {
+            uint32_t plan = 0;
+            if (!s_trivial[p]) {
+                uint32_t dst;
+                if (odd_in_place)
+                    dst = (q & 1) ? kBufOut : kBufTmp;
+                else
+                    dst = ((q_total - 1 - q) & 1) ? kBufTmp : kBufOut;
+                plan = kPlanRun | (prev << kPlanSrcShift) | (dst << kPlanDstShift);
+                prev = dst;
+                ++q;
+            }
+            a.ctrl[kCtrlPlan + p] = plan;
+        }
+        if (q_total == 0 && !a.in_place)
+            a.ctrl[kCtrlPlan + D - 1] = kPlanCopyIn;
+        a.ctrl[kCtrlFinal] = odd_in_place ? 1u : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_pass: one digit pass in a single sweep.
+
+struct PassArgs {
+    Bufs b;
+    uint32_t n;
+    int pass;
+    int shift;
+    uint32_t *ctrl;
+    const uint32_t *digit_base;  // row of this pass
+    uint32_t *status;            // [tiles][256] of this pass
+};
+
+template <typename K, typename V, bool HAS_V>
+__device__ __forceinline__ void copy_tile(const PassArgs &a, uint64_t lo, uint64_t hi,
+                                          uint32_t t, uint32_t threads)
+{
+    const K *ik = pick<const K>(a.b, kBufIn, false);
+    K *ok = pick<K>(a.b, kBufOut, false);
+    for (uint64_t i = lo + t; i < hi; i += threads)
+        ok[i] = ik[i];
+    if constexpr (HAS_V) {
+        const V *iv = pick<const V>(a.b, kBufIn, true);
+        V *ov = pick<V>(a.b, kBufOut, true);
+        for (uint64_t i = lo + t; i < hi; i += threads)
+            ov[i] = iv[i];
+    }
+}
+
+template <typename K, typename V, bool HAS_V>
+__global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassArgs a)
+{
+    using S = PassShape<K, HAS_V>;
+    constexpr int THREADS = S::kThreads;
+    constexpr int ITEMS = S::kItems;
+    constexpr int T = S::kTile;
+    constexpr int W = THREADS / kWave;
+
+    __shared__ uint32_t s_wcnt[W * kRadix];
+    __shared__ uint32_t s_off[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_tmp[8];
+    __shared__ uint32_t s_tile;
+    __shared__ K s_k[T];
+    __shared__ V s_v[HAS_V ? T : 1];
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
+    if (!(plan & kPlanRun)) {
+        if (plan & kPlanCopyIn) {
+            const uint64_t lo = (uint64_t)blockIdx.x * T;
+            const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
+            copy_tile<K, V, HAS_V>(a, lo, hi, t, THREADS);
+        }
+        return;
+    }
+    const uint32_t src = (plan >> kPlanSrcShift) & 3u;
+    const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
+    const K *src_k = pick<const K>(a.b, src, false);
+    K *dst_k = pick<K>(a.b, dstb, false);
+    const V *src_v = HAS_V ? pick<const V>(a.b, src, true) : nullptr;
+    V *dst_v = HAS_V ? pick<V>(a.b, dstb, true) : nullptr;
+
+    if (t == 0)
+        s_tile = atomicAdd(&a.ctrl[kCtrlTileCounter + a.pass], 1u);
+    for (int i = t; i < W * kRadix; i += THREADS)
+        s_wcnt[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t w = t / kWave;
+    const uint32_t lane = t % kWave;
+
+    // load: item j of lane l is element j*64 + l of this wave's run
+    const uint64_t base = (uint64_t)tile * T + (uint64_t)w * (kWave * ITEMS) + lane;
+    K key[ITEMS];
+    V val[HAS_V ? ITEMS : 1];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint64_t idx = base + (uint64_t)j * kWave;
+        key[j] = idx < a.n ? src_k[idx] : KeyTraits<K>::kPad;
+    }
+    if constexpr (HAS_V) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint64_t idx = base + (uint64_t)j * kWave;
+            val[j] = idx < a.n ? src_v[idx] : (V)0;
+        }
+    }
+
+    // count: stable rank of every item among the wave's items of its digit
+    uint32_t *wc = s_wcnt + w * kRadix;
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
+        const uint64_t m = peer_mask(d);
+        const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+        uint32_t old = 0;
+        if (lane == leader)
+            old = atomicAdd(&wc[d], (uint32_t)__popcll(m));
+        old = shfl_idx(old, leader);
+        rank[j] = old + lanes_below(m);
+    }
+    __syncthreads();
+
+    // scan: wave offsets per digit, tile count, publish, tile-local offsets
+    uint32_t cnt = 0;
+    if (t < kRadix) {
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = s_wcnt[ww * kRadix + t];
+            s_wcnt[ww * kRadix + t] = cnt;
+            cnt += c;
+        }
+        __hip_atomic_store(&a.status[(uint64_t)tile * kRadix + t],
+                           (tile == 0 ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t excl = block_exclusive_scan_256<THREADS>(cnt, s_tmp);
+    if (t < kRadix) {
+        uint32_t prefix = 0;
+        if (tile > 0) {
+            int64_t k = (int64_t)tile - 1;
+            while (k >= 0) {
+                const uint32_t s = __hip_atomic_load(&a.status[(uint64_t)k * kRadix + t],
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = s & kFlagMask;
+                if (f == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                prefix += s & kCountMask;
+                if (f == kFlagInc)
+                    break;
+                --k;
+            }
+            __hip_atomic_store(&a.status[(uint64_t)tile * kRadix + t],
+                               kFlagInc | (prefix + cnt), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_off[t] = excl;
+        s_gbase[t] = a.digit_base[t] + prefix - excl;
+    }
+    __syncthreads();
+
+    // place: stage in rank order, then write each digit run out
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
+        const uint32_t pos = s_off[d] + wc[d] + rank[j];
+        s_k[pos] = key[j];
+        if constexpr (HAS_V)
+            s_v[pos] = val[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t pos = i * THREADS + t;
+        const K k = s_k[pos];
+        const uint32_t d = KeyTraits<K>::digit(k, a.shift);
+        const uint32_t dst = s_gbase[d] + pos;
+        if (dst < a.n) {
+            dst_k[dst] = k;
+            if constexpr (HAS_V)
+                dst_v[dst] = s_v[pos];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_finalize: in-place sort with an odd number of moving passes.
+
+template <typename K, typename V, bool HAS_V>
+__global__ void k_finalize(Bufs b, uint32_t n, const uint32_t *ctrl)
+{
+    if (ctrl[kCtrlFinal] != 1u)
+        return;
+    const K *tk = (const K *)b.tmp_k;
+    K *ok = (K *)b.out_k;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        ok[i] = tk[i];
+        if constexpr (HAS_V)
+            ((V *)b.out_v)[i] = ((const V *)b.tmp_v)[i];
+    }
+}
+
+}  // namespace rs
+
+// ===========================================================================
+// Host side: validation, workspace layout, launches.
+
+using namespace rs;
+
+struct ProfRecord {
+    const char *name;
+    int tag;
+    size_t ev;  // index of the first of two events in the pool
+};
+
+struct rs_context {
+    int device = 0;
+    void *own_ws = nullptr;
+    size_t own_ws_bytes = 0;
+    // per-kernel timing (rs_profile_*)
+    bool prof = false;
+    int prof_tag = 0;
+    std::vector<ProfRecord> recs;
+    std::vector<hipEvent_t> events;  // grow-only pool, reused after a reset
+    size_t events_used = 0;
+};
+
+// Launch through f(), bracketed by two events when profiling is on.
+template <typename F>
+static void launch(rs_context *ctx, hipStream_t s, const char *name, F &&f)
+{
+    if (!ctx->prof) {
+        f();
+        return;
+    }
+    while (ctx->events.size() < ctx->events_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            f();
+            return;
+        }
+        ctx->events.push_back(e);
+    }
+    const size_t i = ctx->events_used;
+    ctx->events_used += 2;
+    (void)hipEventRecord(ctx->events[i], s);
+    f();
+    (void)hipEventRecord(ctx->events[i + 1], s);
+    ctx->recs.push_back({name, ctx->prof_tag, i});
+}
+
+static thread_local std::string g_last_error;
+
+static rs_status fail(rs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+static inline uint64_t align_up(uint64_t x, uint64_t a)
+{
+    return (x + a - 1) / a * a;
+}
+
+struct Layout {
+    int d;
+    uint32_t tile;
+    uint64_t tiles;
+    uint64_t off_ctrl, off_hist, off_base, off_status, off_tmp_k, off_tmp_v, total;
+    uint64_t status_bytes;
+};
+
+static Layout make_layout(int key_bytes, bool has_values, uint64_t n)
+{
+    Layout L{};
+    L.d = key_bytes;  // 8-bit digits: one pass per key byte
+    if (key_bytes == 4)
+        L.tile = has_values ? PassShape<uint32_t, true>::kTile : PassShape<uint32_t, false>::kTile;
+    else
+        L.tile = has_values ? PassShape<uint64_t, true>::kTile : PassShape<uint64_t, false>::kTile;
+    L.tiles = (n + L.tile - 1) / L.tile;
+    uint64_t o = 0;
+    L.off_ctrl = o;
+    o = align_up(o + kCtrlWords * 4, 256);
+    L.off_hist = o;
+    o = align_up(o + (uint64_t)L.d * kRadix * 4, 256);
+    L.off_base = o;
+    o = align_up(o + (uint64_t)L.d * kRadix * 4, 256);
+    L.off_status = o;
+    L.status_bytes = (uint64_t)L.d * L.tiles * kRadix * 4;
+    o = align_up(o + L.status_bytes, 256);
+    L.off_tmp_k = o;
+    o = align_up(o + n * key_bytes, 256);
+    L.off_tmp_v = o;
+    o = align_up(o + (has_values ? n * key_bytes : 0), 256);
+    L.total = o;
+    return L;
+}
+
+static bool overlaps(const void *a, uint64_t an, const void *b, uint64_t bn)
+{
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return an && bn && x < y + bn && y < x + an;
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            return;
+        if (prev != dev && hipSetDevice(dev) != hipSuccess)
+            return;
+        ok = true;
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+static rs_status get_workspace(rs_context *ctx, void *ws, size_t ws_bytes, uint64_t need,
+                               void **out)
+{
+    if (ws) {
+        *out = ws;
+        return RS_OK;
+    }
+    if (ctx->own_ws_bytes < need) {
+        if (ctx->own_ws) {
+            (void)hipFree(ctx->own_ws);
+            ctx->own_ws = nullptr;
+            ctx->own_ws_bytes = 0;
+        }
+        if (hipMalloc(&ctx->own_ws, need) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->own_ws = nullptr;
+            return fail(RS_ERR_OUT_OF_MEMORY, "could not allocate %llu bytes of scratch",
+                        (unsigned long long)need);
+        }
+        ctx->own_ws_bytes = need;
+    }
+    (void)ws_bytes;
+    *out = ctx->own_ws;
+    return RS_OK;
+}
+
+static rs_status validate_sort(const rs_context *ctx, int key_bytes, const void *kin,
+                               const void *vin, void *kout, void *vout, bool has_values,
+                               uint64_t n, const void *ws, size_t ws_bytes, Layout *L)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (n >= RS_MAX_ELEMENTS)
+        return fail(RS_ERR_UNSUPPORTED, "n = %llu exceeds the limit of 2^30 - 1 elements",
+                    (unsigned long long)n);
+    *L = make_layout(key_bytes, has_values, n);
+    if (n == 0)
+        return RS_OK;
+    if (!kin || !kout || (has_values && (!vin || !vout)))
+        return fail(RS_ERR_INVALID_ARGUMENT, "NULL data pointer with n > 0");
+    const uintptr_t al = (uintptr_t)key_bytes - 1;
+    if (((uintptr_t)kin & al) || ((uintptr_t)kout & al) ||
+        (has_values && (((uintptr_t)vin & al) || ((uintptr_t)vout & al))))
+        return fail(RS_ERR_INVALID_ARGUMENT, "data pointers must be %d-byte aligned", key_bytes);
+    const uint64_t bytes = n * (uint64_t)key_bytes;
+    if (kin != kout && overlaps(kin, bytes, kout, bytes))
+        return fail(RS_ERR_INVALID_ARGUMENT, "keys_in and keys_out partially overlap");
+    if (has_values) {
+        if (vin != vout && overlaps(vin, bytes, vout, bytes))
+            return fail(RS_ERR_INVALID_ARGUMENT, "vals_in and vals_out partially overlap");
+        if (overlaps(kin, bytes, vin, bytes) || overlaps(kin, bytes, vout, bytes) ||
+            overlaps(kout, bytes, vin, bytes) || overlaps(kout, bytes, vout, bytes))
+            return fail(RS_ERR_INVALID_ARGUMENT, "key and value arrays overlap");
+    }
+    if (ws) {
+        if ((uintptr_t)ws & 255)
+            return fail(RS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+        if (ws_bytes < L->total)
+            return fail(RS_ERR_INVALID_ARGUMENT, "workspace of %zu bytes is below the %llu needed",
+                        ws_bytes, (unsigned long long)L->total);
+        if (overlaps(ws, L->total, kin, bytes) || overlaps(ws, L->total, kout, bytes) ||
+            (has_values && (overlaps(ws, L->total, vin, bytes) || overlaps(ws, L->total, vout, bytes))))
+            return fail(RS_ERR_INVALID_ARGUMENT, "workspace overlaps a data array");
+    }
+    return RS_OK;
+}
+
+template <typename K, bool HAS_V>
+static const char *pass_name()
+{
+    if (sizeof(K) == 4)
+        return HAS_V ? "k_pass_u32_pairs" : "k_pass_u32_keys";
+    return HAS_V ? "k_pass_u64_pairs" : "k_pass_u64_keys";
+}
+
+template <typename K, bool HAS_V>
+static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, K *vout,
+                          uint64_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    Layout L;
+    rs_status st = validate_sort(ctx, sizeof(K), kin, vin, kout, vout, HAS_V, n, ws, ws_bytes, &L);
+    if (st != RS_OK || n == 0)
+        return st;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    void *w = nullptr;
+    st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
+    if (st != RS_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *wb = (char *)w;
+    uint32_t *ctrl = (uint32_t *)(wb + L.off_ctrl);
+    uint32_t *hist = (uint32_t *)(wb + L.off_hist);
+    uint32_t *base = (uint32_t *)(wb + L.off_base);
+    uint32_t *status = (uint32_t *)(wb + L.off_status);
+    // in-place if either array is: the first moving pass must not write its own input
+    const bool in_place = (const void *)kin == (const void *)kout || (HAS_V && vin == vout);
+
+    Bufs b{kin, vin, kout, vout, wb + L.off_tmp_k, HAS_V ? (void *)(wb + L.off_tmp_v) : nullptr};
+
+    launch(ctx, s, "k_init", [&] {
+        hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, ctrl, hist, L.d * kRadix);
+    });
+
+    HistArgs ha{};
+    ha.keys = kin;
+    ha.n = (uint32_t)n;
+    const uint64_t mis = ((uintptr_t)kin & 15) / sizeof(K);
+    ha.head = (uint32_t)std::min<uint64_t>(n, mis ? (16 / sizeof(K)) - mis : 0);
+    ha.nvec = (uint32_t)((n - ha.head) / (16 / sizeof(K)));
+    ha.hist = hist;
+    ha.digit_base = base;
+    ha.ctrl = ctrl;
+    ha.status = (uint4 *)status;
+    ha.status_vec = L.status_bytes / 16;
+    ha.in_place = in_place;
+    const uint64_t hist_blocks = std::max<uint64_t>(
+        1, std::min<uint64_t>(2048, (n + 16383) / 16384));
+    launch(ctx, s, sizeof(K) == 4 ? "k_hist_u32" : "k_hist_u64", [&] {
+        hipLaunchKernelGGL(k_hist<K>, dim3((uint32_t)hist_blocks), dim3(kHistThreads), 0, s, ha);
+    });
+
+    using S = PassShape<K, HAS_V>;
+    for (int p = 0; p < L.d; ++p) {
+        PassArgs pa{};
+        pa.b = b;
+        pa.n = (uint32_t)n;
+        pa.pass = p;
+        pa.shift = p * kRadixBits;
+        pa.ctrl = ctrl;
+        pa.digit_base = base + p * kRadix;
+        pa.status = status + (uint64_t)p * L.tiles * kRadix;
+        launch(ctx, s, pass_name<K, HAS_V>(), [&] {
+            hipLaunchKernelGGL((k_pass<K, K, HAS_V>), dim3((uint32_t)L.tiles), dim3(S::kThreads),
+                               0, s, pa);
+        });
+    }
+    if (in_place) {
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(4096, (n + 255) / 256);
+        launch(ctx, s, "k_finalize", [&] {
+            hipLaunchKernelGGL((k_finalize<K, K, HAS_V>), dim3(blocks), dim3(256), 0, s, b,
+                               (uint32_t)n, (const uint32_t *)ctrl);
+        });
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(RS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return RS_OK;
+}
+
+// ===========================================================================
+// Exported C-ABI.
+
+extern "C" {
+
+rs_status rs_context_create(int device, rs_context **out)
+{
+    if (!out)
+        return fail(RS_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (device < 0)
+        return fail(RS_ERR_INVALID_ARGUMENT, "device must be >= 0");
+    rs_context *c = new (std::nothrow) rs_context();
+    if (c)
+        c->device = device;
+    if (!c)
+        return fail(RS_ERR_OUT_OF_MEMORY, "cannot allocate a context");
+    *out = c;
+    return RS_OK;
+}
+
+void rs_context_destroy(rs_context *ctx)
+{
+    if (!ctx)
+        return;
+    if (ctx->own_ws || !ctx->events.empty()) {
+        DeviceGuard g(ctx->device);
+        if (ctx->own_ws)
+            (void)hipFree(ctx->own_ws);
+        for (hipEvent_t e : ctx->events)
+            (void)hipEventDestroy(e);
+    }
+    delete ctx;
+}
+
+rs_status rs_profile_enable(rs_context *ctx, int enable)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    ctx->prof = enable != 0;
+    return RS_OK;
+}
+
+rs_status rs_profile_tag(rs_context *ctx, int tag)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    ctx->prof_tag = tag;
+    return RS_OK;
+}
+
+rs_status rs_profile_reset(rs_context *ctx)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    ctx->recs.clear();
+    ctx->events_used = 0;
+    return RS_OK;
+}
+
+rs_status rs_profile_read(rs_context *ctx, const char **names, int *tags, float *ms, int max,
+                          int *count)
+{
+    if (!ctx || !count || max < 0 || (max > 0 && (!names || !tags || !ms)))
+        return fail(RS_ERR_INVALID_ARGUMENT, "bad profile_read arguments");
+    *count = (int)ctx->recs.size();
+    if (ctx->recs.empty() || max == 0)
+        return RS_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    const int m = std::min<int>(max, (int)ctx->recs.size());
+    for (int i = 0; i < m; ++i) {
+        const ProfRecord &r = ctx->recs[i];
+        if (hipEventSynchronize(ctx->events[r.ev + 1]) != hipSuccess)
+            return fail(RS_ERR_DEVICE, "event synchronise failed");
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ctx->events[r.ev], ctx->events[r.ev + 1]) != hipSuccess)
+            return fail(RS_ERR_DEVICE, "event elapsed time failed");
+        names[i] = r.name;
+        tags[i] = r.tag;
+        ms[i] = t;
+    }
+    return RS_OK;
+}
+
+rs_status rs_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int has_values,
+                             uint64_t n, size_t *bytes)
+{
+    if (!ctx || !bytes)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx or bytes is NULL");
+    if (key_type != RS_KEY_U32 && key_type != RS_KEY_U64)
+        return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+    if (n >= RS_MAX_ELEMENTS)
+        return fail(RS_ERR_UNSUPPORTED, "n exceeds the limit of 2^30 - 1 elements");
+    *bytes = (size_t)make_layout(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, n).total;
+    return RS_OK;
+}
+
+rs_status rs_sort_keys_u32(rs_context *ctx, const uint32_t *keys_in, uint32_t *keys_out,
+                           uint64_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    return run_sort<uint32_t, false>(ctx, keys_in, nullptr, keys_out, nullptr, n, ws, ws_bytes,
+                                     stream);
+}
+
+rs_status rs_sort_keys_u64(rs_context *ctx, const uint64_t *keys_in, uint64_t *keys_out,
+                           uint64_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    return run_sort<uint64_t, false>(ctx, keys_in, nullptr, keys_out, nullptr, n, ws, ws_bytes,
+                                     stream);
+}
+
+rs_status rs_sort_pairs_u32(rs_context *ctx, const uint32_t *keys_in, const uint32_t *vals_in,
+                            uint32_t *keys_out, uint32_t *vals_out, uint64_t n, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    return run_sort<uint32_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, n, ws, ws_bytes,
+                                    stream);
+}
+
+rs_status rs_sort_pairs_u64(rs_context *ctx, const uint64_t *keys_in, const uint64_t *vals_in,
+                            uint64_t *keys_out, uint64_t *vals_out, uint64_t n, void *ws,
+                            size_t ws_bytes, void *stream)
+{
+    return run_sort<uint64_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, n, ws, ws_bytes,
+                                    stream);
+}
+
+rs_status rs_segmented_workspace_bytes(const rs_context *ctx, rs_key_type key_type,
+                                       int has_values, uint64_t total, uint32_t num_segments,
+                                       size_t *bytes)
+{
+    (void)ctx; (void)key_type; (void)has_values; (void)total; (void)num_segments; (void)bytes;
+    return fail(RS_ERR_UNSUPPORTED, "segmented sort not built yet");
+}
+
+rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *keys_in,
+                            const void *vals_in, void *keys_out, void *vals_out,
+                            const uint64_t *offsets, uint32_t num_segments, uint64_t total,
+                            void *ws, size_t ws_bytes, void *stream)
+{
+    (void)ctx; (void)key_type; (void)keys_in; (void)vals_in; (void)keys_out; (void)vals_out;
+    (void)offsets; (void)num_segments; (void)total; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(RS_ERR_UNSUPPORTED, "segmented sort not built yet");
+}
+
+const char *rs_status_string(rs_status status)
+{
+    switch (status) {
+    case RS_OK: return "ok";
+    case RS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case RS_ERR_UNSUPPORTED: return "unsupported";
+    case RS_ERR_OUT_OF_MEMORY: return "out of memory";
+    case RS_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char *rs_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+"""C-ABI of librs.so on the CPU: every symbol declared in include/rs.h is
+exported, and argument errors are rejected on the host before any HIP call
+(so they can be checked without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1511_03404_amd as rs
+    if not os.path.exists(rs.LIB_PATH):
+        from paper_1511_03404_amd import build
+        build.build()
+    return rs
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:rs_status|void|const char \*)\s*\*?\s*(rs_\w+)\s*\(",
+                                text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("rs_sort_keys_u32", "rs_sort_keys_u64", "rs_sort_pairs_u32",
+                 "rs_sort_pairs_u64", "rs_segmented_sort"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(rs):
+    L = ctypes.CDLL(rs.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) <= set(rs.EXPORTED) | {"rs_segmented_workspace_bytes"}
+
+
+@pytest.fixture()
+def ctx(rs):
+    c = rs.Context(0)
+    yield c
+    c.close()
+
+
+def call_keys(rs, ctx, kin, kout, n, ws=None, ws_bytes=0, bits=32):
+    f = rs.lib().rs_sort_keys_u32 if bits == 32 else rs.lib().rs_sort_keys_u64
+    return f(ctx.handle, kin, kout, n, ws, ws_bytes, None)
+
+
+def test_context_and_workspace_need_no_gpu(rs, ctx):
+    a = ctx.workspace_bytes(32, False, 1 << 20)
+    b = ctx.workspace_bytes(32, True, 1 << 20)
+    c = ctx.workspace_bytes(64, True, 1 << 20)
+    assert 0 < a < b < c
+    assert b >= (1 << 20) * 8  # one ping-pong copy of keys and values
+    assert ctx.workspace_bytes(32, False, 0) > 0
+    with pytest.raises(rs.RSError) as e:
+        ctx.workspace_bytes(32, False, 1 << 30)
+    assert e.value.status == rs.RS_ERR_UNSUPPORTED
+
+
+def test_argument_errors(rs, ctx):
+    L = rs.lib()
+    fake = 0x7F0000000000  # never dereferenced: validation rejects first
+    # n = 0 is a no-op even with NULL pointers
+    assert call_keys(rs, ctx, None, None, 0) == rs.RS_OK
+    assert call_keys(rs, ctx, None, fake, 10) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"NULL" in L.rs_last_error()
+    assert call_keys(rs, ctx, fake + 2, fake + 4096, 10) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"aligned" in L.rs_last_error()
+    assert call_keys(rs, ctx, fake, fake + 4, 8, bits=64) == rs.RS_ERR_INVALID_ARGUMENT
+    # partial overlap of in and out
+    assert call_keys(rs, ctx, fake, fake + 16, 100) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"overlap" in L.rs_last_error()
+    # too many elements
+    assert call_keys(rs, ctx, fake, fake + (1 << 33), 1 << 30) == rs.RS_ERR_UNSUPPORTED
+    # workspace too small / misaligned / overlapping
+    need = ctx.workspace_bytes(32, False, 1000)
+    ws = fake + (1 << 34)
+    assert call_keys(rs, ctx, fake, fake + 8192, 1000, ws, need - 1) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"workspace" in L.rs_last_error()
+    assert call_keys(rs, ctx, fake, fake + 8192, 1000, ws + 4, need) == rs.RS_ERR_INVALID_ARGUMENT
+    assert call_keys(rs, ctx, fake, fake + 8192, 1000, fake + 256, need) == rs.RS_ERR_INVALID_ARGUMENT
+    # pairs: keys and values must not overlap
+    f = L.rs_sort_pairs_u32
+    assert f(ctx.handle, fake, fake + 8, fake + 8192, fake + 16384, 100, None, 0, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    assert f(ctx.handle, fake, None, fake + 8192, fake + 16384, 100, None, 0, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    # NULL context
+    assert L.rs_sort_keys_u32(None, fake, fake + 8192, 10, None, 0, None) == rs.RS_ERR_INVALID_ARGUMENT
+
+
+def test_status_strings(rs):
+    L = rs.lib()
+    for s in range(5):
+        assert L.rs_status_string(s)
+    assert L.rs_status_string(99) == b"unknown status"
+
+
+def test_python_binding_rejects_host_tensors(rs):
+    import torch
+    with pytest.raises(ValueError):
+        rs.sort_keys(torch.zeros(4, dtype=torch.int32))
+    with pytest.raises(TypeError):
+        rs.key_bits(torch.zeros(4, dtype=torch.float32))

@@ -1,0 +1,188 @@
+"""GPU parity: the HIP radix sort (through the C-ABI) against the CPU oracle,
+bit-exact, on seeded inputs of the six distributions; plus the exact O(n)
+stable-sort certificate at the full benchmark sizes, and the edge cases
+(ragged tails, tile boundaries, in-place, unaligned starts, skipped passes)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from tests.certify import certify_stable_sort, certify_sorted_keys
+
+pytestmark = pytest.mark.gpu
+
+TILE = 4096  # keys per tile of the pass kernel
+SIZES = [1, 2, 3, 63, 64, 65, 255, 256, TILE - 1, TILE, TILE + 1, 3 * TILE + 17,
+         (1 << 15) + (1 << 14), 100003]
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1511_03404_amd as rs
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    rs.lib()  # raises if librs.so is missing: there is no fallback
+    return rs
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def gpu_sort(rs, keys, vals=None, in_place=False):
+    kd = dev(keys)
+    if vals is None:
+        out = rs.sort_keys(kd, out=kd if in_place else None)
+        torch.cuda.synchronize()
+        return host(out), None
+    vd = dev(vals)
+    if in_place:
+        ko, vo = rs.sort_pairs(kd, vd, kd, vd)
+    else:
+        ko, vo = rs.sort_pairs(kd, vd)
+    torch.cuda.synchronize()
+    return host(ko), host(vo)
+
+
+def test_native_library_is_loaded(rs):
+    import paper_1511_03404_amd as pkg
+    assert os.path.dirname(pkg.LIB_PATH) == os.path.dirname(os.path.abspath(pkg.__file__))
+    maps = open("/proc/self/maps").read()
+    assert pkg.LIB_PATH in maps
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+def test_parity_ragged_sizes(rs, oracle_lib, bits, pairs, dist):
+    for n in SIZES:
+        print(f"case bits={bits} pairs={pairs} dist={dist} n={n}", flush=True)
+        keys = datagen.keys(dist, n, bits, seed=n)
+        vals = datagen.values(n, bits) if pairs else None
+        ok, ov = oracle_lib.sort(keys, vals)
+        gk, gv = gpu_sort(rs, keys, vals)
+        assert np.array_equal(gk, ok), f"keys differ at n={n}"
+        if pairs:
+            assert np.array_equal(gv, ov), f"values differ at n={n}"
+
+
+def test_empty(rs):
+    for dt in (torch.uint32, torch.uint64):
+        k = torch.empty(0, dtype=dt, device="cuda")
+        assert rs.sort_keys(k).numel() == 0
+        a, b = rs.sort_pairs(k, torch.empty(0, dtype=dt, device="cuda"))
+        assert a.numel() == 0 and b.numel() == 0
+
+
+def test_small_config_uniform_2p20(rs, oracle_lib):
+    """2^20 uniform 32-bit keys from MT19937 seed 1."""
+    keys = datagen.keys("uniform", 1 << 20, 32, seed=1)
+    ok, _ = oracle_lib.sort(keys)
+    gk, _ = gpu_sort(rs, keys)
+    assert np.array_equal(gk, ok)
+
+
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+def test_full_size_u32_pairs(rs, oracle_lib, dist):
+    """2^26 32-bit pairs, value = input index: exact certificate and the oracle."""
+    n = 1 << 26
+    print(f"case u32 pairs n=2^26 dist={dist}", flush=True)
+    keys = datagen.keys(dist, n, 32, seed=1)
+    vals = datagen.values(n, 32)
+    gk, gv = gpu_sort(rs, keys, vals)
+    assert certify_stable_sort(keys, gk, gv) is None
+    ok, ov = oracle_lib.sort(keys, vals)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+def test_full_size_u64(rs, oracle_lib, pairs, dist):
+    """2^25 64-bit keys (random high words), alone and with 64-bit values."""
+    n = 1 << 25
+    print(f"case u64 pairs={pairs} n=2^25 dist={dist}", flush=True)
+    keys = datagen.keys(dist, n, 64, seed=1)
+    vals = datagen.values(n, 64) if pairs else None
+    gk, gv = gpu_sort(rs, keys, vals)
+    if pairs:
+        assert certify_stable_sort(keys, gk, gv) is None
+    else:
+        assert certify_sorted_keys(keys, gk) is None
+    ok, ov = oracle_lib.sort(keys, vals)
+    assert np.array_equal(gk, ok)
+    if pairs:
+        assert np.array_equal(gv, ov)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("mask_bits", [0, 8, 24, None])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_in_place_and_skipped_passes(rs, oracle_lib, bits, mask_bits, pairs):
+    """In-place sorts with 0, 1, 3 and all moving passes (skipped passes
+    change which buffer the result lands in)."""
+    n = 3 * TILE + 5
+    keys = datagen.keys("uniform", n, bits, seed=7)
+    if mask_bits is not None:
+        keys = keys & keys.dtype.type((1 << mask_bits) - 1)
+    vals = datagen.values(n, bits) if pairs else None
+    ok, ov = oracle_lib.sort(keys, vals)
+    for in_place in (False, True):
+        gk, gv = gpu_sort(rs, keys, vals, in_place=in_place)
+        assert np.array_equal(gk, ok)
+        if pairs:
+            assert np.array_equal(gv, ov)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_unaligned_start_and_arbitrary_values(rs, oracle_lib, bits):
+    """Arrays that start one element past a 16-byte boundary; values that are
+    not the index."""
+    n = 2 * TILE + 77
+    keys = datagen.keys("bucket", n, bits, seed=3)
+    vals = datagen.keys("uniform", n, bits, seed=4)
+    kbuf = dev(np.concatenate([keys[:1], keys]))
+    vbuf = dev(np.concatenate([vals[:1], vals]))
+    ko = torch.empty(n + 1, dtype=kbuf.dtype, device="cuda")
+    vo = torch.empty(n + 1, dtype=vbuf.dtype, device="cuda")
+    rs.sort_pairs(kbuf[1:], vbuf[1:], ko[1:], vo[1:])
+    torch.cuda.synchronize()
+    ok, ov = oracle_lib.sort(keys, vals)
+    assert np.array_equal(host(ko[1:]), ok) and np.array_equal(host(vo[1:]), ov)
+
+
+def test_signed_tensors_sort_as_unsigned(rs, oracle_lib):
+    keys = datagen.keys("uniform", 5000, 32, seed=2)
+    t = dev(keys).view(torch.int32)
+    out = rs.sort_keys(t)
+    torch.cuda.synchronize()
+    ok, _ = oracle_lib.sort(keys)
+    assert np.array_equal(host(out.view(torch.uint32)), ok)
+
+
+def test_repeatable(rs):
+    keys = datagen.keys("gaussian", 1 << 20, 32, seed=5)
+    vals = datagen.values(1 << 20)
+    a = gpu_sort(rs, keys, vals)
+    b = gpu_sort(rs, keys, vals)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_caller_workspace_and_streams(rs, oracle_lib):
+    """A caller-provided workspace, reused across calls on a side stream."""
+    n = 50000
+    ctx = rs.context(0)
+    ws = torch.empty(ctx.workspace_bytes(64, True, n), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for seed in (1, 2, 3):
+            keys = datagen.keys("uniform", n, 64, seed=seed)
+            vals = datagen.values(n, 64)
+            ko, vo = rs.sort_pairs(dev(keys), dev(vals), workspace=ws)
+            s.synchronize()
+            ok, ov = oracle_lib.sort(keys, vals)
+            assert np.array_equal(host(ko), ok) and np.array_equal(host(vo), ov)
