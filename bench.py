@@ -31,6 +31,7 @@ WORKLOADS = {
     "u64_pairs": (1 << 25, 64, True, "2^25 u64 key + u64 value pairs (value = input index)"),
     "u32_keys_small": (1 << 20, 32, False, "2^20 u32 keys (latency-bound, cache-resident)"),
 }
+COPY_CALIB_BYTES = 1 << 30  # plain copy used to calibrate the HBM byte counters
 
 
 def parse():
@@ -38,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="u32_pairs", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="u32_pairs", choices=sorted(WORKLOADS) + ["copy_calib"])
     ap.add_argument("--dists", default="all",
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -86,6 +87,18 @@ def main():
     rs.lib()  # fails loudly if librs.so is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "copy_calib":
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE
+        # counter readings calibrate the counters read on the sort kernels
+        a = torch.ones(COPY_CALIB_BYTES // 4, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.warmup + args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "copy_calib", "bytes_read": COPY_CALIB_BYTES,
+                          "bytes_written": COPY_CALIB_BYTES,
+                          "launches": args.warmup + args.steps}), flush=True)
+        return
     n, bits, has_v, wdesc = WORKLOADS[args.workload]
     dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")
     kb = bits // 8

@@ -34,7 +34,6 @@ constexpr uint32_t kCountMask = (1u << 30) - 1;
 
 // Control block (u32 words at the start of the workspace).
 constexpr int kCtrlTileCounter = 0;  // [0, 8): dynamic tile id per pass
-constexpr int kCtrlHistDone = 8;     // workgroups of the histogram kernel that finished
 constexpr int kCtrlPlan = 16;        // [16, 24): plan word per pass
 constexpr int kCtrlFinal = 32;       // final copy: 0 none, 1 tmp -> out
 constexpr int kCtrlWords = 64;
@@ -83,16 +82,21 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 }
 
 // Mask of the lanes of this (full) wave whose 8-bit digit equals ours.
+// For every bit b: s = 0 or ~0 (our bit, sign-extended), bal = the wave's
+// ballot of that bit; bal ^ s marks the lanes whose bit b differs from ours.
+// OR-ing those over the 8 bits (one 3-input v_bitop3 per half: a | (b ^ c))
+// leaves exactly the equal lanes clear.
 __device__ __forceinline__ uint64_t peer_mask(uint32_t d)
 {
-    uint64_t m = ~0ull;
+    uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t s = __ballot(bit);
-        m &= bit ? s : ~s;
+        const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);
+        const uint64_t bal = __ballot(s != 0);
+        diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)bal, s, 0xF6);
+        diff_hi = __builtin_amdgcn_bitop3_b32(diff_hi, (uint32_t)(bal >> 32), s, 0xF6);
     }
-    return m;
+    return ~(((uint64_t)diff_hi << 32) | diff_lo);
 }
 
 __device__ __forceinline__ uint32_t shfl_idx(uint32_t v, uint32_t src_lane)

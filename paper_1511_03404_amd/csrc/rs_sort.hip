@@ -5,12 +5,12 @@
 //
 //   k_init     zero the control block and the digit histograms
 //   k_hist     one read of the keys -> histograms of all d digit positions;
-//              the last workgroup to finish scans each row into digit_base
-//              (the counting sort's exclusive prefix sums) and writes a plan:
+//              also clears the look-back words of every pass
+//   k_plan     one workgroup: scans each histogram row into digit_base (the
+//              counting sort's exclusive prefix sums) and writes a plan:
 //              which passes move data (a pass whose histogram has a single
 //              non-empty digit is the identity and is skipped) and which
-//              buffer each pass reads and writes.  It also clears the
-//              look-back words of every pass.
+//              buffer each pass reads and writes
 //   k_pass     one per digit position: a single sweep over the data that
 //              counts, scans (decoupled look-back across tiles) and places
 //              each tile; see rs_device.h.
@@ -37,11 +37,24 @@ namespace rs {
 // ---------------------------------------------------------------------------
 // Tile shapes.
 
+// Tile of one digit pass: kThreads x kItems elements, one tile per
+// workgroup.
+//   kLookback  predecessor tiles read per look-back round trip
+//   kLdsMatch  find the lanes of a wave that share a digit through a per-wave
+//              LDS table of 64-bit lane masks (each lane ORs its bit into its
+//              digit's slot and reads the slot back) instead of eight ballots
+// Keys are staged in LDS, written out, then the values go through the same
+// buffer; the mask table is only live while ranking and shares it too.  Big
+// tiles amortise the per-tile latencies (tile claim, look-back) and make the
+// digit runs of the scatter longer; 64-bit pairs need a smaller tile to fit
+// the registers of 1024 threads.
 template <typename K, bool HAS_V>
 struct PassShape {
-    static constexpr int kThreads = 256;
+    static constexpr int kThreads = (sizeof(K) == 8 && HAS_V) ? 512 : 1024;
     static constexpr int kItems = 16;
     static constexpr int kTile = kThreads * kItems;
+    static constexpr int kLookback = 8;
+    static constexpr bool kLdsMatch = true;
 };
 
 constexpr int kHistThreads = 256;
@@ -75,8 +88,8 @@ __global__ void k_init(uint32_t *ctrl, uint32_t *hist, int hist_words)
 }
 
 // ---------------------------------------------------------------------------
-// k_hist: all-digit histograms in one read, then (last workgroup) the scans
-// and the pass plan.
+// k_hist: all-digit histograms in one read of the keys; also clears the
+// look-back words of every pass.
 
 struct HistArgs {
     const void *keys;
@@ -84,31 +97,50 @@ struct HistArgs {
     uint32_t head;        // leading keys before the first 16-byte boundary
     uint32_t nvec;        // 16-byte vectors after the head
     uint32_t *hist;       // [d][256]
-    uint32_t *digit_base; // [d][256]
-    uint32_t *ctrl;
     uint4 *status;        // look-back words of all passes, cleared here
     uint64_t status_vec;  // number of uint4 in status
-    int in_place;
 };
 
+// Count one key's D digits into the wave's LDS sub-histograms.
 template <typename K>
-__device__ __forceinline__ void count_key(uint32_t (*sh)[kRadix], K key, uint32_t lane)
+__device__ __forceinline__ void count_one(uint32_t (*sh)[kRadix], K key)
+{
+    constexpr int D = KeyTraits<K>::kBits / kRadixBits;
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+        atomicAdd(&sh[p][KeyTraits<K>::digit(key, p * kRadixBits)], 1u);
+}
+
+// Count a batch of NK keys per thread (a full batch: every lane active).
+// Runs of equal digits are common in skewed inputs (zero, sorted, bucket)
+// and same-address LDS atomics serialise, so per digit position: if the
+// whole wave holds one digit, one lane adds NK*64; if this thread's NK
+// digits are equal, it adds NK once; otherwise one atomic per key.
+template <typename K, int NK>
+__device__ __forceinline__ void count_batch(uint32_t (*sh)[kRadix], const K (&key)[NK])
 {
     constexpr int D = KeyTraits<K>::kBits / kRadixBits;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
-        const uint32_t dg = KeyTraits<K>::digit(key, p * kRadixBits);
-        const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
-        const uint64_t same = __ballot(dg == first);
-        const uint64_t active = __ballot(1);
-        if (same == active) {  // wave-uniform digit: one update for the wave
-            if (lanes_below(active) == 0)
-                atomicAdd(&sh[p][dg], (uint32_t)__popcll(active));
+        uint32_t dg[NK];
+        bool eq = true;
+#pragma unroll
+        for (int i = 0; i < NK; ++i) {
+            dg[i] = KeyTraits<K>::digit(key[i], p * kRadixBits);
+            eq = eq && dg[i] == dg[0];
+        }
+        const uint32_t first = __builtin_amdgcn_readfirstlane(dg[0]);
+        if (__ballot(!(eq && dg[0] == first)) == 0) {
+            if (lane_id() == 0)
+                atomicAdd(&sh[p][first], (uint32_t)(NK * kWave));
+        } else if (eq) {
+            atomicAdd(&sh[p][dg[0]], (uint32_t)NK);
         } else {
-            atomicAdd(&sh[p][dg], 1u);
+#pragma unroll
+            for (int i = 0; i < NK; ++i)
+                atomicAdd(&sh[p][dg[i]], 1u);
         }
     }
-    (void)lane;
 }
 
 template <typename K>
@@ -116,15 +148,14 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
 {
     constexpr int D = KeyTraits<K>::kBits / kRadixBits;
     constexpr int W = kHistThreads / kWave;
-    constexpr int KPV = 16 / (int)sizeof(K);
+    constexpr int KPV = 16 / (int)sizeof(K);  // keys per 16-byte vector
+    constexpr int VPT = 16 / KPV;             // vectors per thread per batch
+    constexpr int NK = VPT * KPV;             // 16 keys per thread per batch
+    constexpr uint32_t BATCH = kHistThreads * VPT;
     __shared__ uint32_t sh[W][D][kRadix];
-    __shared__ uint32_t s_tmp[8];
-    __shared__ int s_last;
-    __shared__ int s_trivial[D];
 
     const uint32_t t = threadIdx.x;
     const uint32_t w = t / kWave;
-    const uint32_t lane = t % kWave;
     for (int i = t; i < W * D * kRadix; i += kHistThreads)
         (&sh[0][0][0])[i] = 0;
 
@@ -137,24 +168,35 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
 
     const K *keys = (const K *)a.keys;
     const uint4 *vec = (const uint4 *)(keys + a.head);
-    for (uint64_t i = gtid; i < a.nvec; i += gstride) {
-        const uint4 v = vec[i];
-        if constexpr (KPV == 4) {
-            count_key<K>(sh[w], (K)v.x, lane);
-            count_key<K>(sh[w], (K)v.y, lane);
-            count_key<K>(sh[w], (K)v.z, lane);
-            count_key<K>(sh[w], (K)v.w, lane);
-        } else {
-            count_key<K>(sh[w], (K)(((uint64_t)v.y << 32) | v.x), lane);
-            count_key<K>(sh[w], (K)(((uint64_t)v.w << 32) | v.z), lane);
+    const uint64_t full_batches = a.nvec / BATCH;
+    for (uint64_t b = blockIdx.x; b < full_batches; b += gridDim.x) {
+        // vector v of this thread: b*BATCH + v*THREADS + t (each wave load is 1 KB contiguous)
+        uint4 v[VPT];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i)
+            v[i] = vec[b * BATCH + (uint64_t)i * kHistThreads + t];
+        K key[NK];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            if constexpr (KPV == 4) {
+                key[4 * i + 0] = (K)v[i].x;
+                key[4 * i + 1] = (K)v[i].y;
+                key[4 * i + 2] = (K)v[i].z;
+                key[4 * i + 3] = (K)v[i].w;
+            } else {
+                key[2 * i + 0] = (K)(((uint64_t)v[i].y << 32) | v[i].x);
+                key[2 * i + 1] = (K)(((uint64_t)v[i].w << 32) | v[i].z);
+            }
         }
+        count_batch<K, NK>(sh[w], key);
     }
-    // unaligned head and ragged tail, element by element
-    const uint64_t tail0 = (uint64_t)a.head + (uint64_t)a.nvec * KPV;
-    const uint64_t extra = a.head + (a.n - tail0);
+    // the rest: unaligned head, vectors after the last full batch, ragged
+    // tail -- element by element, spread over the whole grid
+    const uint64_t rest0 = (uint64_t)a.head + full_batches * BATCH * KPV;
+    const uint64_t extra = a.head + (a.n - rest0);
     for (uint64_t i = gtid; i < extra; i += gstride) {
-        const uint64_t idx = i < a.head ? i : tail0 + (i - a.head);
-        count_key<K>(sh[w], keys[idx], lane);
+        const uint64_t idx = i < a.head ? i : rest0 + (i - a.head);
+        count_one<K>(sh[w], keys[idx]);
     }
     __syncthreads();
 
@@ -167,19 +209,32 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
             atomicAdd(&a.hist[i], s);
     }
 
-    // last workgroup: scans and plan
-    __threadfence();
-    __syncthreads();
-    if (t == 0)
-        s_last = atomicAdd(&a.ctrl[kCtrlHistDone], 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last)
-        return;
-    __threadfence();
+}
+
+// ---------------------------------------------------------------------------
+// k_plan (one workgroup): digit_base = exclusive scan of each histogram row
+// (the counting sort's starting offsets), and the plan of every pass.  A
+// pass whose digit is the same for all n keys is the identity permutation
+// and is skipped; the remaining passes alternate between the output and the
+// scratch copy so that the last one lands in the output.
+
+struct PlanArgs {
+    const uint32_t *hist;
+    uint32_t *digit_base;
+    uint32_t *ctrl;
+    uint32_t n;
+    int in_place;
+};
+
+template <int D>
+__global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
+{
+    __shared__ uint32_t s_tmp[8];
+    __shared__ int s_trivial[D];
+    const uint32_t t = threadIdx.x;
     for (int p = 0; p < D; ++p) {
-        const uint32_t c = __hip_atomic_load(&a.hist[p * kRadix + t], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t ex = block_exclusive_scan_256<kHistThreads>(c, s_tmp);
+        const uint32_t c = a.hist[p * kRadix + t];
+        const uint32_t ex = block_exclusive_scan_256<kRadix>(c, s_tmp);
         a.digit_base[p * kRadix + t] = ex;
         const int triv = __syncthreads_or(c == a.n);
         if (t == 0)
@@ -224,6 +279,7 @@ struct PassArgs {
     uint32_t *ctrl;
     const uint32_t *digit_base;  // row of this pass
     uint32_t *status;            // [tiles][256] of this pass
+    uint32_t num_tiles;
 };
 
 template <typename K, typename V, bool HAS_V>
@@ -242,6 +298,42 @@ __device__ __forceinline__ void copy_tile(const PassArgs &a, uint64_t lo, uint64
     }
 }
 
+// p[i] = v.  For 4-byte elements the byte offset fits in 32 bits (n < 2^30),
+// which lets the store use a scalar base and a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ void store_at(T *p, uint32_t i, T v)
+{
+    if constexpr (sizeof(T) == 4)
+        *(T *)((char *)p + (i << 2)) = v;
+    else
+        p[i] = v;
+}
+
+template <typename K, typename V, bool HAS_V, int ITEMS>
+__device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t valid, uint32_t off0,
+                                          K (&key)[ITEMS], V (&val)[HAS_V ? ITEMS : 1], bool full)
+{
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            key[j] = tk[off0 + j * kWave];
+        if constexpr (HAS_V) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                val[j] = tv[off0 + j * kWave];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            key[j] = off0 + j * kWave < valid ? tk[off0 + j * kWave] : KeyTraits<K>::kPad;
+        if constexpr (HAS_V) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                val[j] = off0 + j * kWave < valid ? tv[off0 + j * kWave] : (V)0;
+        }
+    }
+}
+
 template <typename K, typename V, bool HAS_V>
 __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassArgs a)
 {
@@ -250,14 +342,20 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
     constexpr int ITEMS = S::kItems;
     constexpr int T = S::kTile;
     constexpr int W = THREADS / kWave;
+    constexpr int LBW = S::kLookback;
+    static_assert(sizeof(V) == sizeof(K), "values have the key's width");
+    constexpr size_t kStageBytes = (size_t)T * sizeof(K);
+    static_assert(!S::kLdsMatch || (size_t)W * kRadix * 8 <= kStageBytes,
+                  "the mask table lives in the staging buffer");
 
-    __shared__ uint32_t s_wcnt[W * kRadix];
-    __shared__ uint32_t s_off[kRadix];
+    __shared__ uint32_t s_wcnt[W * kRadix];  // per wave and digit: count, then base in tile
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_tmp[8];
     __shared__ uint32_t s_tile;
-    __shared__ K s_k[T];
-    __shared__ V s_v[HAS_V ? T : 1];
+    __shared__ __attribute__((aligned(16))) unsigned char s_stage[kStageBytes];
+    K *s_k = (K *)s_stage;
+    V *s_v = (V *)s_stage;
+    uint64_t *s_mask = (uint64_t *)s_stage;
 
     const uint32_t t = threadIdx.x;
     const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
@@ -271,54 +369,70 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
     }
     const uint32_t src = (plan >> kPlanSrcShift) & 3u;
     const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
-    const K *src_k = pick<const K>(a.b, src, false);
-    K *dst_k = pick<K>(a.b, dstb, false);
-    const V *src_v = HAS_V ? pick<const V>(a.b, src, true) : nullptr;
-    V *dst_v = HAS_V ? pick<V>(a.b, dstb, true) : nullptr;
 
     if (t == 0)
         s_tile = atomicAdd(&a.ctrl[kCtrlTileCounter + a.pass], 1u);
-    for (int i = t; i < W * kRadix; i += THREADS)
+    for (int i = t; i < W * kRadix; i += THREADS) {
         s_wcnt[i] = 0;
+        if constexpr (S::kLdsMatch)
+            s_mask[i] = 0;
+    }
+    // this digit's starting offset, fetched early (used after the look-back)
+    const uint32_t dbase = t < kRadix ? a.digit_base[t] : 0u;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint32_t w = t / kWave;
     const uint32_t lane = t % kWave;
 
-    // load: item j of lane l is element j*64 + l of this wave's run
-    const uint64_t base = (uint64_t)tile * T + (uint64_t)w * (kWave * ITEMS) + lane;
+    // load: item j of lane l is element j*64 + l of this wave's run; the
+    // tile's base pointer is uniform, per-lane offsets are 32-bit
+    const uint64_t tile_base = (uint64_t)tile * T;
+    const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tile_base);
+    const uint32_t off0 = w * (kWave * ITEMS) + lane;
     K key[ITEMS];
     V val[HAS_V ? ITEMS : 1];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint64_t idx = base + (uint64_t)j * kWave;
-        key[j] = idx < a.n ? src_k[idx] : KeyTraits<K>::kPad;
-    }
-    if constexpr (HAS_V) {
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint64_t idx = base + (uint64_t)j * kWave;
-            val[j] = idx < a.n ? src_v[idx] : (V)0;
-        }
-    }
+    load_tile<K, V, HAS_V, ITEMS>(pick<const K>(a.b, src, false) + tile_base,
+                                  HAS_V ? pick<const V>(a.b, src, true) + tile_base : nullptr,
+                                  valid, off0, key, val, valid == (uint32_t)T);
 
-    // count: stable rank of every item among the wave's items of its digit
+    // count: stable rank of every item among the wave's items of its digit,
+    // items visited in input order
     uint32_t *wc = s_wcnt + w * kRadix;
     uint32_t rank[ITEMS];
+    if constexpr (S::kLdsMatch) {
+        uint64_t *wm = s_mask + w * kRadix;
+        const uint64_t lane_bit = 1ull << lane;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
-        const uint64_t m = peer_mask(d);
-        const uint32_t leader = (uint32_t)__builtin_ctzll(m);
-        uint32_t old = 0;
-        if (lane == leader)
-            old = atomicAdd(&wc[d], (uint32_t)__popcll(m));
-        old = shfl_idx(old, leader);
-        rank[j] = old + lanes_below(m);
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
+            atomicOr(&wm[d], lane_bit);
+            const uint64_t m = wm[d];  // every lane of the wave holding digit d
+            const uint32_t c = wc[d];
+            const uint32_t below = lanes_below(m);
+            rank[j] = c + below;
+            if (below == 0) {  // lowest lane of the group: advance and clear
+                wc[d] = c + (uint32_t)__popcll(m);
+                wm[d] = 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
+            const uint64_t m = peer_mask(d);
+            const uint32_t below = lanes_below(m);
+            const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+            uint32_t old = 0;
+            if (below == 0)
+                old = atomicAdd(&wc[d], (uint32_t)__popcll(m));
+            old = shfl_idx(old, leader);
+            rank[j] = old + below;
+        }
     }
     __syncthreads();
 
-    // scan: wave offsets per digit, tile count, publish, tile-local offsets
+    // scan: wave offsets per digit, tile count, publish the aggregate,
+    // tile-local offsets
     uint32_t cnt = 0;
     if (t < kRadix) {
 #pragma unroll
@@ -333,52 +447,77 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
     }
     const uint32_t excl = block_exclusive_scan_256<THREADS>(cnt, s_tmp);
     if (t < kRadix) {
+        // decoupled look-back: read LBW predecessors per round trip, add
+        // their counts in order up to the first inclusive one; on a tile
+        // that has not published yet, wait and re-read from there
         uint32_t prefix = 0;
-        if (tile > 0) {
-            int64_t k = (int64_t)tile - 1;
-            while (k >= 0) {
-                const uint32_t s = __hip_atomic_load(&a.status[(uint64_t)k * kRadix + t],
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t f = s & kFlagMask;
-                if (f == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+        int64_t k = (int64_t)tile - 1;
+        while (k >= 0) {
+            uint32_t st[LBW];
+#pragma unroll
+            for (int i = 0; i < LBW; ++i)
+                st[i] = (k - i >= 0)
+                            ? __hip_atomic_load(&a.status[(uint64_t)(k - i) * kRadix + t],
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : kFlagInc;
+            int used = 0;
+            bool done = false;
+#pragma unroll
+            for (int i = 0; i < LBW; ++i) {
+                if (!done && used == i) {
+                    const uint32_t f = st[i] & kFlagMask;
+                    if (f != 0) {
+                        prefix += st[i] & kCountMask;
+                        done = f == kFlagInc;
+                        used = i + 1;
+                    }
                 }
-                prefix += s & kCountMask;
-                if (f == kFlagInc)
-                    break;
-                --k;
             }
-            __hip_atomic_store(&a.status[(uint64_t)tile * kRadix + t],
-                               kFlagInc | (prefix + cnt), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (done)
+                break;
+            k -= used;
+            if (used < LBW)
+                __builtin_amdgcn_s_sleep(1);
         }
-        s_off[t] = excl;
-        s_gbase[t] = a.digit_base[t] + prefix - excl;
+        if (tile > 0)
+            __hip_atomic_store(&a.status[(uint64_t)tile * kRadix + t], kFlagInc | (prefix + cnt),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_gbase[t] = dbase + prefix - excl;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww)
+            s_wcnt[ww * kRadix + t] += excl;
     }
     __syncthreads();
 
-    // place: stage in rank order, then write each digit run out
+    // place: stage the keys in rank order, then write each digit run out
+    // with consecutive lanes on consecutive addresses; then the values
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
-        const uint32_t pos = s_off[d] + wc[d] + rank[j];
-        s_k[pos] = key[j];
-        if constexpr (HAS_V)
-            s_v[pos] = val[j];
+        rank[j] += wc[KeyTraits<K>::digit(key[j], a.shift)];  // position in the tile
+        s_k[rank[j]] = key[j];
     }
     __syncthreads();
+    K *dk = pick<K>(a.b, dstb, false);
+    uint32_t dst[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t pos = i * THREADS + t;
         const K k = s_k[pos];
-        const uint32_t d = KeyTraits<K>::digit(k, a.shift);
-        const uint32_t dst = s_gbase[d] + pos;
-        if (dst < a.n) {
-            dst_k[dst] = k;
-            if constexpr (HAS_V)
-                dst_v[dst] = s_v[pos];
-        }
+        dst[i] = s_gbase[KeyTraits<K>::digit(k, a.shift)] + pos;
+        if (dst[i] < a.n)
+            store_at(dk, dst[i], k);
+    }
+    if constexpr (HAS_V) {
+        V *dv = pick<V>(a.b, dstb, true);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            s_v[rank[j]] = val[j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (dst[i] < a.n)
+                store_at(dv, dst[i], s_v[i * THREADS + t]);
     }
 }
 
@@ -423,6 +562,7 @@ struct rs_context {
     std::vector<ProfRecord> recs;
     std::vector<hipEvent_t> events;  // grow-only pool, reused after a reset
     size_t events_used = 0;
+    uint32_t cus = 0;  // compute units, queried on first use
 };
 
 // Launch through f(), bracketed by two events when profiling is on.
@@ -530,6 +670,22 @@ struct DeviceGuard {
 };
 
 }  // namespace
+
+// Compute units of the context's device (queried once).
+static uint32_t ctx_cus(rs_context *ctx)
+{
+    if (ctx->cus == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, ctx->device) !=
+                hipSuccess ||
+            v < 1) {
+            (void)hipGetLastError();
+            v = 1;
+        }
+        ctx->cus = (uint32_t)v;
+    }
+    return ctx->cus;
+}
 
 static rs_status get_workspace(rs_context *ctx, void *ws, size_t ws_bytes, uint64_t need,
                                void **out)
@@ -643,15 +799,18 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     ha.head = (uint32_t)std::min<uint64_t>(n, mis ? (16 / sizeof(K)) - mis : 0);
     ha.nvec = (uint32_t)((n - ha.head) / (16 / sizeof(K)));
     ha.hist = hist;
-    ha.digit_base = base;
-    ha.ctrl = ctrl;
     ha.status = (uint4 *)status;
     ha.status_vec = L.status_bytes / 16;
-    ha.in_place = in_place;
     const uint64_t hist_blocks = std::max<uint64_t>(
         1, std::min<uint64_t>(2048, (n + 16383) / 16384));
     launch(ctx, s, sizeof(K) == 4 ? "k_hist_u32" : "k_hist_u64", [&] {
         hipLaunchKernelGGL(k_hist<K>, dim3((uint32_t)hist_blocks), dim3(kHistThreads), 0, s, ha);
+    });
+
+    PlanArgs pl{hist, base, ctrl, (uint32_t)n, in_place};
+    launch(ctx, s, "k_plan", [&] {
+        hipLaunchKernelGGL(k_plan<KeyTraits<K>::kBits / kRadixBits>, dim3(1), dim3(kRadix), 0, s,
+                           pl);
     });
 
     using S = PassShape<K, HAS_V>;
@@ -664,6 +823,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         pa.ctrl = ctrl;
         pa.digit_base = base + p * kRadix;
         pa.status = status + (uint64_t)p * L.tiles * kRadix;
+        pa.num_tiles = (uint32_t)L.tiles;
         launch(ctx, s, pass_name<K, HAS_V>(), [&] {
             hipLaunchKernelGGL((k_pass<K, K, HAS_V>), dim3((uint32_t)L.tiles), dim3(S::kThreads),
                                0, s, pa);
