@@ -34,6 +34,78 @@ WORKLOADS = {
 COPY_CALIB_BYTES = 1 << 30  # plain copy used to calibrate the HBM byte counters
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("paper_1511_03404_amd/csrc/rs_sort.hip", "paper_1511_03404_amd/csrc/rs_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+PASS_KERNEL = {
+    "u32_pairs": "void rs::k_pass<unsigned int, unsigned int, true>",
+    "u64_keys": "void rs::k_pass<unsigned long, unsigned long, false>",
+    "u64_pairs": "void rs::k_pass<unsigned long, unsigned long, true>",
+    "u32_keys_small": "void rs::k_pass<unsigned int, unsigned int, false>",
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per digit-pass launch from the committed counter summary,
+    or None if it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    w = t.get("workloads", {}).get(workload)
+    return None if w is None else w.get("traffic_bytes_per_launch")
+
+
+def summarize_pmc(root):
+    """Turn rocprofv3 --pmc runs into the per-launch traffic summary.
+
+    Expects <root>/<workload>/{FETCH_SIZE,WRITE_SIZE}/run_counter_collection.csv
+    for the workloads, and <root>/copy/{FETCH_SIZE,WRITE_SIZE}/... for the
+    1 GiB plain copy (bench.py --workload copy_calib) that scales each
+    counter to bytes."""
+    import csv
+
+    def mean(path, prefix):
+        v = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+             if r["Kernel_Name"].startswith(prefix)]
+        return (sum(v) / len(v), len(v)) if v else (None, 0)
+
+    cf, _ = mean(os.path.join(root, "copy", "FETCH_SIZE", "run_counter_collection.csv"),
+                 "__amd_rocclr_copyBuffer")
+    cw, _ = mean(os.path.join(root, "copy", "WRITE_SIZE", "run_counter_collection.csv"),
+                 "__amd_rocclr_copyBuffer")
+    fs, ws = COPY_CALIB_BYTES / (cf * 1024), COPY_CALIB_BYTES / (cw * 1024)
+    out = {"kernel_source_sha256_16": kernel_source_hash(),
+           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
+           "calibration": f"1 GiB plain copy (torch copy_, runtime blit kernel): FETCH_SIZE "
+                          f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB",
+           "workloads": {}}
+    for w, k in PASS_KERNEL.items():
+        fp = os.path.join(root, w, "FETCH_SIZE", "run_counter_collection.csv")
+        wp = os.path.join(root, w, "WRITE_SIZE", "run_counter_collection.csv")
+        if not (os.path.exists(fp) and os.path.exists(wp)):
+            continue
+        f, nf = mean(fp, k)
+        wr, _ = mean(wp, k)
+        out["workloads"][w] = {"kernel": k, "fetch_kib_per_launch": round(f, 1),
+                               "write_kib_per_launch": round(wr, 1),
+                               "traffic_bytes_per_launch": int(f * 1024 * fs + wr * 1024 * ws),
+                               "launches_sampled": nf}
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +116,8 @@ def parse():
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="print the traffic summary of rocprofv3 --pmc runs under DIR and exit")
     return ap.parse_args()
 
 
@@ -72,6 +146,9 @@ def cpu_baseline(bits, has_v, dists, sample_log2):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
                           "a design note, not implemented", "n_gpus": args.gpus}))
@@ -169,7 +246,8 @@ def main():
         bytes_per_launch = 2 * n * (kb + vb)  # read + write of keys and values, one digit
         achieved = bytes_per_launch / (avg * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(args.workload),
                     "kernel": pass_name, "avg_launch_ms": round(avg, 5),
                     "launches": len(pass_ms), "bytes_per_launch": bytes_per_launch,
                     "input": dists[ref]}

@@ -43,6 +43,7 @@ namespace rs {
 //   kLdsMatch  find the lanes of a wave that share a digit through a per-wave
 //              LDS table of 64-bit lane masks (each lane ORs its bit into its
 //              digit's slot and reads the slot back) instead of eight ballots
+//   kGroup     consecutive tiles claimed as a group (see claim_tile)
 // Keys are staged in LDS, written out, then the values go through the same
 // buffer; the mask table is only live while ranking and shares it too.  Big
 // tiles amortise the per-tile latencies (tile claim, look-back) and make the
@@ -55,6 +56,7 @@ struct PassShape {
     static constexpr int kTile = kThreads * kItems;
     static constexpr int kLookback = 8;
     static constexpr bool kLdsMatch = true;
+    static constexpr int kGroup = 8;
 };
 
 constexpr int kHistThreads = 256;
@@ -279,8 +281,74 @@ struct PassArgs {
     uint32_t *ctrl;
     const uint32_t *digit_base;  // row of this pass
     uint32_t *status;            // [tiles][256] of this pass
+    uint32_t *claims;            // per-XCD claim counters and group lists
     uint32_t num_tiles;
+    uint32_t num_groups;
 };
+
+// Which compute die (XCD) this wave runs on, from the XCC_ID hardware register.
+__device__ __forceinline__ uint32_t xcc_id()
+{
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 7u;
+}
+
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// Claim the next tile for this workgroup (called by one thread).
+//
+// The digit runs of consecutive tiles meet inside shared cache lines.  When
+// the two tiles run on different XCDs, each XCD's L2 writes back a partial
+// line, which costs far more than one full line.  So consecutive tiles are
+// handed out in groups of GROUP, and the tiles of a group go to workgroups of
+// one XCD that start at about the same time:
+//   * every XCD keeps its own claim counter; claim k on XCD x takes tile
+//     k % GROUP of the XCD's group number k / GROUP;
+//   * the claim with k % GROUP == 0 opens that group: it takes the next group
+//     from the global counter and publishes the group's id in the XCD's
+//     list; the other claims of the same group wait for that id (the opener
+//     is running, so the wait is short).
+// Groups are opened in global order and the tiles of one XCD's groups
+// increase with its claim counter, so the lowest unfinished tile is always
+// held or next to be claimed by a running workgroup of its XCD (workgroups
+// keep claiming until the groups run out): the look-back waits cannot
+// depend on a workgroup that has not started.
+//
+// claims layout: [0, 8) per-XCD claim counters, then [8 + x*G + j] the id+1
+// of group j of XCD x (0 = not yet published, kNoTile = no group left).
+template <int GROUP>
+__device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
+{
+    uint32_t *ctr = &a.ctrl[kCtrlTileCounter + a.pass];
+    if constexpr (GROUP == 1) {
+        (void)xcc;
+        const uint32_t t = atomicAdd(ctr, 1u);
+        return t < a.num_tiles ? t : kNoTile;
+    } else {
+        uint32_t *list = a.claims + 8 + (uint64_t)xcc * a.num_groups;
+        while (true) {
+            const uint32_t k = atomicAdd(&a.claims[xcc], 1u);
+            const uint32_t j = k / GROUP, i = k % GROUP;
+            if (j >= a.num_groups)
+                return kNoTile;
+            uint32_t v;
+            if (i == 0) {
+                const uint32_t g = atomicAdd(ctr, 1u);
+                v = g < a.num_groups ? g + 1 : kNoTile;
+                __hip_atomic_store(&list[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                while ((v = __hip_atomic_load(&list[j], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                    __builtin_amdgcn_s_sleep(1);
+            }
+            if (v == kNoTile)
+                return kNoTile;
+            const uint32_t t = (v - 1) * GROUP + i;
+            if (t < a.num_tiles)
+                return t;
+            // past the end of a short last group: claim again
+        }
+    }
+}
 
 template <typename K, typename V, bool HAS_V>
 __device__ __forceinline__ void copy_tile(const PassArgs &a, uint64_t lo, uint64_t hi,
@@ -361,28 +429,35 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
     const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
     if (!(plan & kPlanRun)) {
         if (plan & kPlanCopyIn) {
-            const uint64_t lo = (uint64_t)blockIdx.x * T;
-            const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
-            copy_tile<K, V, HAS_V>(a, lo, hi, t, THREADS);
+            for (uint64_t tl = blockIdx.x; tl < a.num_tiles; tl += gridDim.x) {
+                const uint64_t lo = tl * T;
+                const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
+                copy_tile<K, V, HAS_V>(a, lo, hi, t, THREADS);
+            }
         }
         return;
     }
     const uint32_t src = (plan >> kPlanSrcShift) & 3u;
     const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
 
+    // this digit's starting offset, fetched early (used after the look-back)
+    const uint32_t dbase = t < kRadix ? a.digit_base[t] : 0u;
+    const uint32_t w = t / kWave;
+    const uint32_t lane = t % kWave;
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+
+    while (true) {
     if (t == 0)
-        s_tile = atomicAdd(&a.ctrl[kCtrlTileCounter + a.pass], 1u);
+        s_tile = claim_tile<S::kGroup>(a, xcc);
     for (int i = t; i < W * kRadix; i += THREADS) {
         s_wcnt[i] = 0;
         if constexpr (S::kLdsMatch)
             s_mask[i] = 0;
     }
-    // this digit's starting offset, fetched early (used after the look-back)
-    const uint32_t dbase = t < kRadix ? a.digit_base[t] : 0u;
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint32_t w = t / kWave;
-    const uint32_t lane = t % kWave;
+    if (tile == kNoTile)
+        break;
 
     // load: item j of lane l is element j*64 + l of this wave's run; the
     // tile's base pointer is uniform, per-lane offsets are 32-bit
@@ -519,6 +594,8 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
             if (dst[i] < a.n)
                 store_at(dv, dst[i], s_v[i * THREADS + t]);
     }
+    __syncthreads();  // LDS is reused by the next tile
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +690,8 @@ struct Layout {
     uint32_t tile;
     uint64_t tiles;
     uint64_t off_ctrl, off_hist, off_base, off_status, off_tmp_k, off_tmp_v, total;
-    uint64_t status_bytes;
+    uint64_t status_bytes;  // look-back words and claim counters of all passes
+    uint64_t claim_words;
 };
 
 static Layout make_layout(int key_bytes, bool has_values, uint64_t n)
@@ -633,7 +711,8 @@ static Layout make_layout(int key_bytes, bool has_values, uint64_t n)
     L.off_base = o;
     o = align_up(o + (uint64_t)L.d * kRadix * 4, 256);
     L.off_status = o;
-    L.status_bytes = (uint64_t)L.d * L.tiles * kRadix * 4;
+    L.claim_words = 8 + 8 * L.tiles;  // per-XCD counters + per-XCD group lists
+    L.status_bytes = align_up((uint64_t)L.d * (L.tiles * kRadix + L.claim_words) * 4, 16);
     o = align_up(o + L.status_bytes, 256);
     L.off_tmp_k = o;
     o = align_up(o + n * key_bytes, 256);
@@ -814,6 +893,17 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     });
 
     using S = PassShape<K, HAS_V>;
+    // workgroups loop over claimed tiles: launch only what fits on the device
+    // at once (more would start at the end just to find no work)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pass<K, K, HAS_V>, S::kThreads,
+                                                     0) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    const uint32_t pass_grid =
+        (uint32_t)std::min<uint64_t>(L.tiles, (uint64_t)per_cu * ctx_cus(ctx));
     for (int p = 0; p < L.d; ++p) {
         PassArgs pa{};
         pa.b = b;
@@ -823,9 +913,11 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         pa.ctrl = ctrl;
         pa.digit_base = base + p * kRadix;
         pa.status = status + (uint64_t)p * L.tiles * kRadix;
+        pa.claims = status + (uint64_t)L.d * L.tiles * kRadix + (uint64_t)p * L.claim_words;
         pa.num_tiles = (uint32_t)L.tiles;
+        pa.num_groups = (uint32_t)((L.tiles + S::kGroup - 1) / S::kGroup);
         launch(ctx, s, pass_name<K, HAS_V>(), [&] {
-            hipLaunchKernelGGL((k_pass<K, K, HAS_V>), dim3((uint32_t)L.tiles), dim3(S::kThreads),
+            hipLaunchKernelGGL((k_pass<K, K, HAS_V>), dim3(pass_grid), dim3(S::kThreads),
                                0, s, pa);
         });
     }
