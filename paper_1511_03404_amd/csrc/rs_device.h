@@ -143,4 +143,34 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
     return excl;
 }
 
+// Stable rank of ITEMS keys per lane among the keys of this wave that share
+// their digit.  Items are visited j = 0..ITEMS-1 and, within an item, by lane,
+// which must be the input order of the wave's elements.  wc is the wave's
+// 256-entry running count per digit (zeroed by the caller); wm a 256-entry
+// table of 64-bit lane masks (zeroed by the caller, left zeroed).  For every
+// item each lane ORs its bit into its digit's slot and reads the slot back:
+// that is the mask of lanes holding the same digit.  The group's lowest lane
+// advances the count and clears the slot.  rank = count before the group +
+// lanes of the group below this one.  After the call wc holds the wave's
+// total per digit.
+template <typename K, typename Traits, int ITEMS>
+__device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], int shift, uint32_t *wc,
+                                          uint64_t *wm, uint32_t lane, uint32_t (&rank)[ITEMS])
+{
+    const uint64_t lane_bit = 1ull << lane;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t d = Traits::digit(key[j], shift);
+        atomicOr(&wm[d], lane_bit);
+        const uint64_t m = wm[d];
+        const uint32_t c = wc[d];
+        const uint32_t below = lanes_below(m);
+        rank[j] = c + below;
+        if (below == 0) {
+            wc[d] = c + (uint32_t)__popcll(m);
+            wm[d] = 0;
+        }
+    }
+}
+
 }  // namespace rs

@@ -30,7 +30,9 @@
 #include <vector>
 
 #include "rs.h"
+#include "rs_block.h"
 #include "rs_device.h"
+#include "rs_segmented.h"
 
 namespace rs {
 
@@ -402,98 +404,58 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
     }
 }
 
-template <typename K, typename V, bool HAS_V>
-__global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassArgs a)
+// LDS of one digit pass over tiles of T elements.
+template <typename K, typename V, int THREADS, int T>
+struct PassLds {
+    static constexpr int W = THREADS / kWave;
+    static constexpr size_t kStageBytes = (size_t)T * sizeof(K);
+    uint32_t wcnt[W * kRadix];  // per wave and digit: count, then base in tile
+    uint32_t gbase[kRadix];
+    uint32_t tmp[8];
+    uint32_t tile;
+    __attribute__((aligned(16))) unsigned char stage[kStageBytes];
+};
+
+// One tile of a digit pass (the paper's counting sort, Section 2.6, spread
+// over workgroups): rank, publish the tile's digit counts, decoupled
+// look-back over tiles [first_tile, tile), stage in LDS, write the digit
+// runs.  The tile's elements are tk/tv[0, valid); destination index i of the
+// digit-sorted sequence is dk/dv[i] for i < limit.  dbase (threads < 256) is
+// the digit's starting offset in that sequence.  Ends with a barrier.
+template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS, int LBW, bool LDS_MATCH>
+__device__ __forceinline__ void pass_tile(PassLds<K, V, THREADS, THREADS * ITEMS> &L,
+                                          const K *tk, const V *tv, K *dk, V *dv,
+                                          uint32_t valid, uint32_t limit, uint32_t tile,
+                                          uint32_t first_tile, uint32_t *status, uint32_t dbase,
+                                          int shift)
 {
-    using S = PassShape<K, HAS_V>;
-    constexpr int THREADS = S::kThreads;
-    constexpr int ITEMS = S::kItems;
-    constexpr int T = S::kTile;
+    constexpr int T = THREADS * ITEMS;
     constexpr int W = THREADS / kWave;
-    constexpr int LBW = S::kLookback;
     static_assert(sizeof(V) == sizeof(K), "values have the key's width");
-    constexpr size_t kStageBytes = (size_t)T * sizeof(K);
-    static_assert(!S::kLdsMatch || (size_t)W * kRadix * 8 <= kStageBytes,
+    static_assert(!LDS_MATCH || (size_t)W * kRadix * 8 <= (size_t)T * sizeof(K),
                   "the mask table lives in the staging buffer");
-
-    __shared__ uint32_t s_wcnt[W * kRadix];  // per wave and digit: count, then base in tile
-    __shared__ uint32_t s_gbase[kRadix];
-    __shared__ uint32_t s_tmp[8];
-    __shared__ uint32_t s_tile;
-    __shared__ __attribute__((aligned(16))) unsigned char s_stage[kStageBytes];
-    K *s_k = (K *)s_stage;
-    V *s_v = (V *)s_stage;
-    uint64_t *s_mask = (uint64_t *)s_stage;
-
+    K *s_k = (K *)L.stage;
+    V *s_v = (V *)L.stage;
+    uint64_t *s_mask = (uint64_t *)L.stage;
     const uint32_t t = threadIdx.x;
-    const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
-    if (!(plan & kPlanRun)) {
-        if (plan & kPlanCopyIn) {
-            for (uint64_t tl = blockIdx.x; tl < a.num_tiles; tl += gridDim.x) {
-                const uint64_t lo = tl * T;
-                const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
-                copy_tile<K, V, HAS_V>(a, lo, hi, t, THREADS);
-            }
-        }
-        return;
-    }
-    const uint32_t src = (plan >> kPlanSrcShift) & 3u;
-    const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
-
-    // this digit's starting offset, fetched early (used after the look-back)
-    const uint32_t dbase = t < kRadix ? a.digit_base[t] : 0u;
     const uint32_t w = t / kWave;
     const uint32_t lane = t % kWave;
-    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
-
-    while (true) {
-    if (t == 0)
-        s_tile = claim_tile<S::kGroup>(a, xcc);
-    for (int i = t; i < W * kRadix; i += THREADS) {
-        s_wcnt[i] = 0;
-        if constexpr (S::kLdsMatch)
-            s_mask[i] = 0;
-    }
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile == kNoTile)
-        break;
-
-    // load: item j of lane l is element j*64 + l of this wave's run; the
-    // tile's base pointer is uniform, per-lane offsets are 32-bit
-    const uint64_t tile_base = (uint64_t)tile * T;
-    const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tile_base);
     const uint32_t off0 = w * (kWave * ITEMS) + lane;
+    uint32_t *wc = L.wcnt + w * kRadix;
+
+    // load: item j of lane l is element j*64 + l of this wave's run
     K key[ITEMS];
     V val[HAS_V ? ITEMS : 1];
-    load_tile<K, V, HAS_V, ITEMS>(pick<const K>(a.b, src, false) + tile_base,
-                                  HAS_V ? pick<const V>(a.b, src, true) + tile_base : nullptr,
-                                  valid, off0, key, val, valid == (uint32_t)T);
+    load_tile<K, V, HAS_V, ITEMS>(tk, tv, valid, off0, key, val, valid == (uint32_t)T);
 
-    // count: stable rank of every item among the wave's items of its digit,
-    // items visited in input order
-    uint32_t *wc = s_wcnt + w * kRadix;
+    // count: stable rank of every item among the wave's items of its digit
     uint32_t rank[ITEMS];
-    if constexpr (S::kLdsMatch) {
-        uint64_t *wm = s_mask + w * kRadix;
-        const uint64_t lane_bit = 1ull << lane;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
-            atomicOr(&wm[d], lane_bit);
-            const uint64_t m = wm[d];  // every lane of the wave holding digit d
-            const uint32_t c = wc[d];
-            const uint32_t below = lanes_below(m);
-            rank[j] = c + below;
-            if (below == 0) {  // lowest lane of the group: advance and clear
-                wc[d] = c + (uint32_t)__popcll(m);
-                wm[d] = 0;
-            }
-        }
+    if constexpr (LDS_MATCH) {
+        wave_rank<K, KeyTraits<K>, ITEMS>(key, shift, wc, s_mask + w * kRadix, lane, rank);
     } else {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t d = KeyTraits<K>::digit(key[j], a.shift);
+            const uint32_t d = KeyTraits<K>::digit(key[j], shift);
             const uint64_t m = peer_mask(d);
             const uint32_t below = lanes_below(m);
             const uint32_t leader = (uint32_t)__builtin_ctzll(m);
@@ -512,27 +474,28 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
     if (t < kRadix) {
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) {
-            const uint32_t c = s_wcnt[ww * kRadix + t];
-            s_wcnt[ww * kRadix + t] = cnt;
+            const uint32_t c = L.wcnt[ww * kRadix + t];
+            L.wcnt[ww * kRadix + t] = cnt;
             cnt += c;
         }
-        __hip_atomic_store(&a.status[(uint64_t)tile * kRadix + t],
-                           (tile == 0 ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
+        __hip_atomic_store(&status[(uint64_t)tile * kRadix + t],
+                           (tile == first_tile ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    const uint32_t excl = block_exclusive_scan_256<THREADS>(cnt, s_tmp);
+    const uint32_t excl = block_exclusive_scan_256<THREADS>(cnt, L.tmp);
     if (t < kRadix) {
         // decoupled look-back: read LBW predecessors per round trip, add
         // their counts in order up to the first inclusive one; on a tile
         // that has not published yet, wait and re-read from there
         uint32_t prefix = 0;
         int64_t k = (int64_t)tile - 1;
-        while (k >= 0) {
+        const int64_t lo = first_tile;
+        while (k >= lo) {
             uint32_t st[LBW];
 #pragma unroll
             for (int i = 0; i < LBW; ++i)
-                st[i] = (k - i >= 0)
-                            ? __hip_atomic_load(&a.status[(uint64_t)(k - i) * kRadix + t],
+                st[i] = (k - i >= lo)
+                            ? __hip_atomic_load(&status[(uint64_t)(k - i) * kRadix + t],
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                             : kFlagInc;
             int used = 0;
@@ -554,13 +517,13 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
             if (used < LBW)
                 __builtin_amdgcn_s_sleep(1);
         }
-        if (tile > 0)
-            __hip_atomic_store(&a.status[(uint64_t)tile * kRadix + t], kFlagInc | (prefix + cnt),
+        if (tile != first_tile)
+            __hip_atomic_store(&status[(uint64_t)tile * kRadix + t], kFlagInc | (prefix + cnt),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_gbase[t] = dbase + prefix - excl;
+        L.gbase[t] = dbase + prefix - excl;
 #pragma unroll
         for (int ww = 0; ww < W; ++ww)
-            s_wcnt[ww * kRadix + t] += excl;
+            L.wcnt[ww * kRadix + t] += excl;
     }
     __syncthreads();
 
@@ -568,22 +531,20 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
     // with consecutive lanes on consecutive addresses; then the values
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        rank[j] += wc[KeyTraits<K>::digit(key[j], a.shift)];  // position in the tile
+        rank[j] += wc[KeyTraits<K>::digit(key[j], shift)];  // position in the tile
         s_k[rank[j]] = key[j];
     }
     __syncthreads();
-    K *dk = pick<K>(a.b, dstb, false);
     uint32_t dst[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t pos = i * THREADS + t;
         const K k = s_k[pos];
-        dst[i] = s_gbase[KeyTraits<K>::digit(k, a.shift)] + pos;
-        if (dst[i] < a.n)
+        dst[i] = L.gbase[KeyTraits<K>::digit(k, shift)] + pos;
+        if (dst[i] < limit)
             store_at(dk, dst[i], k);
     }
     if constexpr (HAS_V) {
-        V *dv = pick<V>(a.b, dstb, true);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j)
@@ -591,11 +552,132 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (dst[i] < a.n)
+            if (dst[i] < limit)
                 store_at(dv, dst[i], s_v[i * THREADS + t]);
     }
     __syncthreads();  // LDS is reused by the next tile
+}
+
+template <typename K, typename V, bool HAS_V>
+__global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassArgs a)
+{
+    using S = PassShape<K, HAS_V>;
+    constexpr int THREADS = S::kThreads;
+    constexpr int T = S::kTile;
+    __shared__ PassLds<K, V, THREADS, T> L;
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
+    if (!(plan & kPlanRun)) {
+        if (plan & kPlanCopyIn) {
+            for (uint64_t tl = blockIdx.x; tl < a.num_tiles; tl += gridDim.x) {
+                const uint64_t lo = tl * T;
+                const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
+                copy_tile<K, V, HAS_V>(a, lo, hi, t, THREADS);
+            }
+        }
+        return;
     }
+    const uint32_t src = (plan >> kPlanSrcShift) & 3u;
+    const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
+    const K *sk = pick<const K>(a.b, src, false);
+    const V *sv = HAS_V ? pick<const V>(a.b, src, true) : nullptr;
+    K *dk = pick<K>(a.b, dstb, false);
+    V *dv = HAS_V ? pick<V>(a.b, dstb, true) : nullptr;
+    // this digit's starting offset, fetched early (used after the look-back)
+    const uint32_t dbase = t < kRadix ? a.digit_base[t] : 0u;
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    while (true) {
+        if (t == 0)
+            L.tile = claim_tile<S::kGroup>(a, xcc);
+        for (int i = t; i < PassLds<K, V, THREADS, T>::W * kRadix; i += THREADS) {
+            L.wcnt[i] = 0;
+            if constexpr (S::kLdsMatch)
+                ((uint64_t *)L.stage)[i] = 0;
+        }
+        __syncthreads();
+        const uint32_t tile = L.tile;
+        if (tile == kNoTile)
+            break;
+        const uint64_t tb = (uint64_t)tile * T;
+        const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tb);
+        pass_tile<K, V, HAS_V, THREADS, S::kItems, S::kLookback, S::kLdsMatch>(
+            L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile, 0, a.status, dbase,
+            a.shift);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_seg_pass: one digit pass over the tiles of every large segment of a
+// segmented sort.  Each segment's tiles are consecutive in the batched tile
+// sequence and its look-back chain starts at its first tile.
+
+struct SegPassArgs {
+    const void *src_k;
+    const void *src_v;
+    void *dst_k;
+    void *dst_v;
+    const SegLarge *large;
+    const uint32_t *tile_seg;
+    const uint32_t *seg_base;  // [large segment][d][256]
+    uint32_t *ctrl;            // segmented control block
+    uint32_t *status;          // look-back words of this pass
+    uint32_t *claims;          // claim counters of this pass
+    uint32_t max_tiles;        // tiles the workspace holds
+    int pass;
+    int shift;
+    int d;
+};
+
+template <typename K, typename V, bool HAS_V>
+__global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_seg_pass(SegPassArgs a)
+{
+    using S = PassShape<K, HAS_V>;
+    constexpr int THREADS = S::kThreads;
+    constexpr int T = S::kTile;
+    __shared__ PassLds<K, V, THREADS, T> L;
+    const uint32_t t = threadIdx.x;
+    PassArgs pa{};
+    pa.ctrl = a.ctrl + (kSegPassCounter - kCtrlTileCounter);
+    pa.pass = a.pass;
+    pa.claims = a.claims;
+    pa.num_tiles = std::min(a.ctrl[kSegTiles], a.max_tiles);
+    pa.num_groups = (pa.num_tiles + S::kGroup - 1) / S::kGroup;
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    while (true) {
+        if (t == 0)
+            L.tile = claim_tile<S::kGroup>(pa, xcc);
+        for (int i = t; i < PassLds<K, V, THREADS, T>::W * kRadix; i += THREADS) {
+            L.wcnt[i] = 0;
+            if constexpr (S::kLdsMatch)
+                ((uint64_t *)L.stage)[i] = 0;
+        }
+        __syncthreads();
+        const uint32_t tile = L.tile;
+        if (tile == kNoTile)
+            break;
+        const uint32_t seg = a.tile_seg[tile];
+        const SegLarge rec = a.large[seg];
+        const uint32_t lt = tile - rec.tile_start;
+        const uint32_t first = lt * T;
+        const uint32_t valid = rec.size > first ? std::min<uint32_t>(T, rec.size - first) : 0u;
+        const uint32_t dbase =
+            t < kRadix ? a.seg_base[((uint64_t)seg * a.d + a.pass) * kRadix + t] : 0u;
+        const uint64_t off = rec.start + (uint64_t)lt * T;
+        pass_tile<K, V, HAS_V, THREADS, S::kItems, S::kLookback, S::kLdsMatch>(
+            L, (const K *)a.src_k + off, HAS_V ? (const V *)a.src_v + off : nullptr,
+            (K *)a.dst_k + rec.start, HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
+            tile, rec.tile_start, a.status, dbase, a.shift);
+    }
+}
+
+// Grid-stride fill of n uint4 with zero (clears counters without a memset
+// node, so a captured graph stays memset-free).
+__global__ void k_zero(uint4 *p, uint64_t n)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = make_uint4(0, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -852,11 +934,31 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
         return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    using B = BlockShape<K, HAS_V>;
+    if (n <= (uint64_t)B::kMediumCap) {
+        // the whole array fits one workgroup's LDS: one launch, all passes
+        BlockArgs ba{kin, vin, kout, vout, nullptr, nullptr, nullptr, n};
+        if (n <= (uint64_t)B::kSmallCap) {
+            launch(ctx, s, "k_block_sort_small", [&] {
+                hipLaunchKernelGGL((k_block_sort<K, K, HAS_V, B::kSmallThreads, B::kItems>),
+                                   dim3(1), dim3(B::kSmallThreads), 0, s, ba);
+            });
+        } else {
+            launch(ctx, s, "k_block_sort_medium", [&] {
+                hipLaunchKernelGGL((k_block_sort<K, K, HAS_V, B::kMediumThreads, B::kItems>),
+                                   dim3(1), dim3(B::kMediumThreads), 0, s, ba);
+            });
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return fail(RS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        return RS_OK;
+    }
     void *w = nullptr;
     st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
     if (st != RS_OK)
         return st;
-    hipStream_t s = (hipStream_t)stream;
     char *wb = (char *)w;
     uint32_t *ctrl = (uint32_t *)(wb + L.off_ctrl);
     uint32_t *hist = (uint32_t *)(wb + L.off_hist);
@@ -929,6 +1031,201 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         });
     }
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(RS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Segmented sort host side.
+
+static constexpr uint64_t kSegMaxTotal = (uint64_t)1 << 36;
+
+struct SegLayout {
+    int d;
+    uint64_t max_tiles;
+    uint64_t claim_words;
+    uint64_t off_ctrl, off_small, off_medium, off_large, off_base, off_tile_seg, off_status,
+        status_bytes, off_tmp_k, off_tmp_v, total;
+};
+
+static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total, uint32_t nseg)
+{
+    SegLayout L{};
+    L.d = key_bytes;
+    const uint64_t T = key_bytes == 4 ? (has_values ? PassShape<uint32_t, true>::kTile
+                                                    : PassShape<uint32_t, false>::kTile)
+                                      : (has_values ? PassShape<uint64_t, true>::kTile
+                                                    : PassShape<uint64_t, false>::kTile);
+    // every large segment adds at most one partial tile
+    L.max_tiles = total / T + nseg + 1;
+    L.claim_words = 8 + 8 * L.max_tiles;
+    uint64_t o = 0;
+    L.off_ctrl = o;
+    o = align_up(o + kSegWords * 4, 256);
+    L.off_small = o;
+    o = align_up(o + (uint64_t)nseg * sizeof(SegRange), 256);
+    L.off_medium = o;
+    o = align_up(o + (uint64_t)nseg * sizeof(SegRange), 256);
+    L.off_large = o;
+    o = align_up(o + (uint64_t)nseg * sizeof(SegLarge), 256);
+    L.off_base = o;
+    o = align_up(o + (uint64_t)nseg * L.d * kRadix * 4, 256);
+    L.off_tile_seg = o;
+    o = align_up(o + L.max_tiles * 4, 256);
+    L.off_status = o;
+    L.status_bytes = align_up((uint64_t)L.d * (L.max_tiles * kRadix + L.claim_words) * 4, 16);
+    o = align_up(o + L.status_bytes, 256);
+    L.off_tmp_k = o;
+    o = align_up(o + total * key_bytes, 256);
+    L.off_tmp_v = o;
+    o = align_up(o + (has_values ? total * key_bytes : 0), 256);
+    L.total = o;
+    return L;
+}
+
+template <typename K, bool HAS_V>
+static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin, void *kout,
+                               void *vout, const uint64_t *offsets, uint32_t nseg, uint64_t total,
+                               void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (total >= kSegMaxTotal)
+        return fail(RS_ERR_UNSUPPORTED, "total exceeds 2^36 elements");
+    if (HAS_V && (!vin || !vout))
+        return fail(RS_ERR_INVALID_ARGUMENT, "values need both vals_in and vals_out");
+    const SegLayout L = make_seg_layout(sizeof(K), HAS_V, total, nseg);
+    if (nseg == 0 || total == 0)
+        return RS_OK;
+    if (!offsets)
+        return fail(RS_ERR_INVALID_ARGUMENT, "offsets is NULL");
+    if (!kin || !kout)
+        return fail(RS_ERR_INVALID_ARGUMENT, "NULL data pointer with total > 0");
+    const uintptr_t al = sizeof(K) - 1;
+    if (((uintptr_t)kin & al) || ((uintptr_t)kout & al) || ((uintptr_t)offsets & 7) ||
+        (HAS_V && (((uintptr_t)vin & al) || ((uintptr_t)vout & al))))
+        return fail(RS_ERR_INVALID_ARGUMENT, "misaligned pointer");
+    const uint64_t bytes = total * sizeof(K);
+    if (kin != kout && overlaps(kin, bytes, kout, bytes))
+        return fail(RS_ERR_INVALID_ARGUMENT, "keys_in and keys_out partially overlap");
+    if (HAS_V) {
+        if (vin != vout && overlaps(vin, bytes, vout, bytes))
+            return fail(RS_ERR_INVALID_ARGUMENT, "vals_in and vals_out partially overlap");
+        if (overlaps(kin, bytes, vin, bytes) || overlaps(kin, bytes, vout, bytes) ||
+            overlaps(kout, bytes, vin, bytes) || overlaps(kout, bytes, vout, bytes))
+            return fail(RS_ERR_INVALID_ARGUMENT, "key and value arrays overlap");
+    }
+    if (ws) {
+        if ((uintptr_t)ws & 255)
+            return fail(RS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+        if (ws_bytes < L.total)
+            return fail(RS_ERR_INVALID_ARGUMENT, "workspace of %zu bytes is below the %llu needed",
+                        ws_bytes, (unsigned long long)L.total);
+        if (overlaps(ws, L.total, kin, bytes) || overlaps(ws, L.total, kout, bytes) ||
+            (HAS_V && (overlaps(ws, L.total, vin, bytes) || overlaps(ws, L.total, vout, bytes))))
+            return fail(RS_ERR_INVALID_ARGUMENT, "workspace overlaps a data array");
+    }
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    void *w = nullptr;
+    rs_status st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
+    if (st != RS_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    char *wb = (char *)w;
+    uint32_t *ctrl = (uint32_t *)(wb + L.off_ctrl);
+    SegRange *small_list = (SegRange *)(wb + L.off_small);
+    SegRange *medium_list = (SegRange *)(wb + L.off_medium);
+    SegLarge *large = (SegLarge *)(wb + L.off_large);
+    uint32_t *seg_base = (uint32_t *)(wb + L.off_base);
+    uint32_t *tile_seg = (uint32_t *)(wb + L.off_tile_seg);
+    uint32_t *status = (uint32_t *)(wb + L.off_status);
+    void *tmp_k = wb + L.off_tmp_k;
+    void *tmp_v = HAS_V ? (void *)(wb + L.off_tmp_v) : nullptr;
+    using B = BlockShape<K, HAS_V>;
+    using S = PassShape<K, HAS_V>;
+    const uint32_t cus = ctx_cus(ctx);
+
+    launch(ctx, s, "k_zero", [&] {
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (uint4 *)ctrl,
+                           (uint64_t)kSegWords * 4 / 16);
+    });
+    launch(ctx, s, "k_zero", [&] {
+        const uint64_t nvec = L.status_bytes / 16;
+        const uint32_t g = (uint32_t)std::min<uint64_t>(4096, (nvec + 255) / 256);
+        hipLaunchKernelGGL(k_zero, dim3(std::max(1u, g)), dim3(256), 0, s, (uint4 *)status, nvec);
+    });
+    SegClassifyArgs ca{offsets, nseg, total, (uint32_t)L.max_tiles, ctrl, small_list, medium_list,
+                       large, tile_seg, kin, vin, kout, vout, (uint32_t)B::kSmallCap,
+                       (uint32_t)B::kMediumCap, (uint32_t)S::kTile};
+    launch(ctx, s, "k_seg_classify", [&] {
+        const uint32_t g = std::min<uint32_t>(1024, (nseg + 255) / 256);
+        hipLaunchKernelGGL((k_seg_classify<K, HAS_V>), dim3(std::max(1u, g)), dim3(256), 0, s, ca);
+    });
+    // small and medium segments: persistent workgroups over the device lists
+    auto grid_of = [&](const void *kernel, int threads) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) !=
+                hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        return (uint32_t)per_cu * cus;
+    };
+    {
+        BlockArgs ba{kin, vin, kout, vout, small_list, ctrl + kSegSmallLen, ctrl + kSegSmallClaim,
+                     0};
+        auto kern = k_block_sort<K, K, HAS_V, B::kSmallThreads, B::kItems>;
+        const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, B::kSmallThreads), nseg);
+        launch(ctx, s, "k_block_sort_small", [&] {
+            hipLaunchKernelGGL(kern, dim3(g), dim3(B::kSmallThreads), 0, s, ba);
+        });
+    }
+    {
+        BlockArgs ba{kin, vin, kout, vout, medium_list, ctrl + kSegMediumLen,
+                     ctrl + kSegMediumClaim, 0};
+        auto kern = k_block_sort<K, K, HAS_V, B::kMediumThreads, B::kItems>;
+        const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, B::kMediumThreads), nseg);
+        launch(ctx, s, "k_block_sort_medium", [&] {
+            hipLaunchKernelGGL(kern, dim3(g), dim3(B::kMediumThreads), 0, s, ba);
+        });
+    }
+    // large segments: per-segment histograms, then the batched digit passes,
+    // in -> tmp -> out -> ... (an even number of passes ends in out)
+    {
+        SegHistArgs ha{kin, large, ctrl, seg_base};
+        auto kern = k_seg_hist<K>;
+        const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, 256), nseg);
+        launch(ctx, s, "k_seg_hist", [&] { hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, ha); });
+    }
+    {
+        auto kern = k_seg_pass<K, K, HAS_V>;
+        const uint32_t g = grid_of((const void *)kern, S::kThreads);
+        for (int p = 0; p < L.d; ++p) {
+            SegPassArgs pa{};
+            pa.src_k = p == 0 ? kin : ((p & 1) ? tmp_k : kout);
+            pa.src_v = p == 0 ? vin : ((p & 1) ? tmp_v : vout);
+            pa.dst_k = (p & 1) ? kout : tmp_k;
+            pa.dst_v = (p & 1) ? vout : tmp_v;
+            pa.large = large;
+            pa.tile_seg = tile_seg;
+            pa.seg_base = seg_base;
+            pa.ctrl = ctrl;
+            pa.status = status + (uint64_t)p * L.max_tiles * kRadix;
+            pa.claims = status + (uint64_t)L.d * L.max_tiles * kRadix + (uint64_t)p * L.claim_words;
+            pa.max_tiles = (uint32_t)L.max_tiles;
+            pa.pass = p;
+            pa.shift = p * kRadixBits;
+            pa.d = L.d;
+            launch(ctx, s, sizeof(K) == 4 ? "k_seg_pass_u32" : "k_seg_pass_u64", [&] {
+                hipLaunchKernelGGL(kern, dim3(g), dim3(S::kThreads), 0, s, pa);
+            });
+        }
+    }
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(RS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return RS_OK;
@@ -1067,8 +1364,16 @@ rs_status rs_segmented_workspace_bytes(const rs_context *ctx, rs_key_type key_ty
                                        int has_values, uint64_t total, uint32_t num_segments,
                                        size_t *bytes)
 {
-    (void)ctx; (void)key_type; (void)has_values; (void)total; (void)num_segments; (void)bytes;
-    return fail(RS_ERR_UNSUPPORTED, "segmented sort not built yet");
+    if (!ctx || !bytes)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx or bytes is NULL");
+    if (key_type != RS_KEY_U32 && key_type != RS_KEY_U64)
+        return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+    if (total >= kSegMaxTotal)
+        return fail(RS_ERR_UNSUPPORTED, "total exceeds 2^36 elements");
+    *bytes = (size_t)make_seg_layout(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, total,
+                                     num_segments)
+                 .total;
+    return RS_OK;
 }
 
 rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *keys_in,
@@ -1076,9 +1381,21 @@ rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *k
                             const uint64_t *offsets, uint32_t num_segments, uint64_t total,
                             void *ws, size_t ws_bytes, void *stream)
 {
-    (void)ctx; (void)key_type; (void)keys_in; (void)vals_in; (void)keys_out; (void)vals_out;
-    (void)offsets; (void)num_segments; (void)total; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(RS_ERR_UNSUPPORTED, "segmented sort not built yet");
+    if (key_type == RS_KEY_U32) {
+        if (vals_in || vals_out)
+            return run_segmented<uint32_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                                 num_segments, total, ws, ws_bytes, stream);
+        return run_segmented<uint32_t, false>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                              num_segments, total, ws, ws_bytes, stream);
+    }
+    if (key_type == RS_KEY_U64) {
+        if (vals_in || vals_out)
+            return run_segmented<uint64_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                                 num_segments, total, ws, ws_bytes, stream);
+        return run_segmented<uint64_t, false>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                              num_segments, total, ws, ws_bytes, stream);
+    }
+    return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
 }
 
 const char *rs_status_string(rs_status status)

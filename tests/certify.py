@@ -66,3 +66,38 @@ def multiset_hash(keys):
         x *= np.uint64(0xBF58476D1CE4E5B9)
         x ^= x >> np.uint64(32)
         return int(x.sum(dtype=np.uint64)), int(np.bitwise_xor.reduce(x)) if x.size else 0
+
+
+def certify_segmented(in_keys, out_keys, out_vals, offsets):
+    """Segmented form of the certificate, with value = index within the
+    segment: every segment of the output is the unique stable sort of the
+    same segment of the input.  Elements outside every segment are not
+    checked here."""
+    in_keys = np.asarray(in_keys)
+    out_keys = np.asarray(out_keys)
+    out_vals = np.asarray(out_vals).astype(np.int64)
+    off = np.asarray(offsets, dtype=np.int64)
+    sizes = np.diff(off)
+    if (sizes < 0).any():
+        return "offsets decrease"
+    seg = np.repeat(np.arange(sizes.size), sizes)
+    starts = np.repeat(off[:-1], sizes)
+    lo, hi = int(off[0]), int(off[-1])
+    ok_, ov = out_keys[lo:hi], out_vals[lo:hi]
+    if ((ov < 0) | (ov >= np.repeat(sizes, sizes))).any():
+        return "value out of its segment"
+    g = starts + ov
+    seen = np.zeros(hi - lo, dtype=bool)
+    seen[g - lo] = True
+    if not seen.all():
+        return "values are not a permutation within each segment"
+    if not np.array_equal(ok_, in_keys[g]):
+        return "a key does not travel with its value"
+    same = seg[1:] == seg[:-1]
+    dk = ok_[1:] >= ok_[:-1]
+    if (same & ~dk).any():
+        return "keys decrease inside a segment"
+    eq = same & (ok_[1:] == ok_[:-1])
+    if (eq & (ov[1:] <= ov[:-1])).any():
+        return "equal keys out of input order (unstable)"
+    return None

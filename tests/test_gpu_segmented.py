@@ -1,0 +1,157 @@
+"""GPU parity of the batched segmented sort (one enqueue for many uneven
+independent sorts) against the CPU oracle applied per segment."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from tests.certify import certify_segmented
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_1511_03404_amd as rs
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    rs.lib()
+    return rs
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_seg(rs, keys, vals, offsets, total_out=None, in_place=False, sentinel=None):
+    kd = dev(keys)
+    vd = dev(vals) if vals is not None else None
+    off = dev(np.asarray(offsets, dtype=np.uint64).view(np.int64))
+    if in_place:
+        ko, vo = kd, vd
+    else:
+        ko = torch.empty_like(kd)
+        vo = torch.empty_like(vd) if vd is not None else None
+        if sentinel is not None:
+            ko.fill_(sentinel)
+            if vo is not None:
+                vo.fill_(sentinel)
+    rs.segmented_sort(kd, vd, off, ko, vo)
+    torch.cuda.synchronize()
+    return ko.cpu().numpy(), (vo.cpu().numpy() if vo is not None else None)
+
+
+def local_index(offsets, total, bits):
+    off = np.asarray(offsets, dtype=np.int64)
+    v = np.zeros(total, dtype=np.int64)
+    sizes = np.diff(off)
+    v[off[0]:off[-1]] = np.arange(off[-1] - off[0]) - np.repeat(off[:-1] - off[0], sizes)
+    return v.astype(np.uint32 if bits == 32 else np.uint64)
+
+
+CASES = {
+    # sizes straddling every class boundary: empty, single, small cap 4096,
+    # medium cap (16384, or 8192 for 64-bit pairs), tile multiples
+    "edges": [0, 1, 2, 0, 4095, 4096, 4097, 8191, 8192, 8193, 16383, 16384, 16385, 1, 0,
+              32768, 32769, 49153, 3, 100003],
+    "all_tiny": [16, 17, 1, 0, 31, 64, 2, 5] * 40,
+    "one_giant": [300001],
+    "many_large": [20000 + 1237 * i for i in range(12)],
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_segmented_matches_oracle(rs, oracle_lib, case, bits, pairs):
+    sizes = CASES[case]
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    total = int(off[-1])
+    print(f"case {case} bits={bits} pairs={pairs} total={total}", flush=True)
+    keys = datagen.keys("bucket", total, bits, seed=len(sizes))
+    keys[::3] = datagen.keys("uniform", keys[::3].size, bits, seed=7)
+    vals = local_index(off, total, bits) if pairs else None
+    gk, gv = run_seg(rs, keys, vals, off)
+    ok, ov = oracle_lib.segmented_sort(keys, vals, off)
+    assert np.array_equal(gk, ok)
+    if pairs:
+        assert np.array_equal(gv, ov)
+        assert certify_segmented(keys, gk, gv, off) is None
+
+
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+@pytest.mark.parametrize("bits", [32, 64])
+def test_segmented_distributions(rs, oracle_lib, dist, bits):
+    """Skewed inputs make whole waves share a digit (and partial last waves
+    share one by chance): every distribution, every size class."""
+    sizes = [17, 4000, 0, 9000, 16500, 1, 60482, 33333, 100000, 66]
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    total = int(off[-1])
+    print(f"case dist={dist} bits={bits}", flush=True)
+    keys = datagen.keys(dist, total, bits, seed=11)
+    vals = local_index(off, total, bits)
+    gk, gv = run_seg(rs, keys, vals, off)
+    ok, ov = oracle_lib.segmented_sort(keys, vals, off)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_gaps_outside_segments_untouched(rs, oracle_lib, bits):
+    """Segments need not cover the array: elements outside stay as they were
+    in the output buffer."""
+    total = 70000
+    off = np.array([100, 5000, 5000, 40000, 69000], dtype=np.uint64)
+    keys = datagen.keys("uniform", total, bits, seed=2)
+    vals = datagen.keys("uniform", total, bits, seed=3)
+    sent = 12345
+    gk, gv = run_seg(rs, keys, vals, off, sentinel=sent)
+    ok, ov = oracle_lib.segmented_sort(keys, vals, off)
+    lo, hi = int(off[0]), int(off[-1])
+    assert np.array_equal(gk[lo:hi], ok[lo:hi]) and np.array_equal(gv[lo:hi], ov[lo:hi])
+    assert (gk[:lo] == sent).all() and (gk[hi:] == sent).all()
+    assert (gv[:lo] == sent).all() and (gv[hi:] == sent).all()
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_in_place(rs, oracle_lib, bits):
+    sizes = [3000, 0, 17000, 5, 40000, 9000]
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    total = int(off[-1])
+    keys = datagen.keys("gaussian", total, bits, seed=4)
+    vals = local_index(off, total, bits)
+    gk, gv = run_seg(rs, keys, vals, off, in_place=True)
+    ok, ov = oracle_lib.segmented_sort(keys, vals, off)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
+def test_log_uniform_batch_certified(rs, oracle_lib):
+    """2000 segments with log-uniform sizes in [16, 2^20] (the batched
+    workload's size law at a tenth of its segment count): the segmented
+    certificate on every element, the oracle on a sample of segments."""
+    keys, vals, off = datagen.segmented(num_segments=2000, bits=32, seed=1)
+    print(f"case log-uniform batch total={int(off[-1])}", flush=True)
+    gk, gv = run_seg(rs, keys, vals, off)
+    assert certify_segmented(keys, gk, gv, off) is None
+    rng = np.random.RandomState(0)
+    for s in rng.choice(2000, size=20, replace=False):
+        a, b = int(off[s]), int(off[s + 1])
+        ok, ov = oracle_lib.sort(keys[a:b], vals[a:b])
+        assert np.array_equal(gk[a:b], ok) and np.array_equal(gv[a:b], ov)
+
+
+def test_repeatable_with_caller_workspace(rs):
+    keys, vals, off = datagen.segmented(num_segments=300, lo_log2=4, hi_log2=17, bits=64, seed=5)
+    ctx = rs.context(0)
+    ws = torch.empty(ctx.segmented_workspace_bytes(64, True, keys.size, 300), dtype=torch.uint8,
+                     device="cuda")
+    kd, vd = dev(keys), dev(vals)
+    offd = dev(off.view(np.int64))
+    outs = []
+    for _ in range(2):
+        ko, vo = rs.segmented_sort(kd, vd, offd, workspace=ws)
+        torch.cuda.synchronize()
+        outs.append((ko.cpu().numpy(), vo.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert certify_segmented(keys, outs[0][0], outs[0][1], off) is None

@@ -13,9 +13,11 @@ from tests.certify import certify_stable_sort, certify_sorted_keys
 
 pytestmark = pytest.mark.gpu
 
-TILE = 4096  # keys per tile of the pass kernel
-SIZES = [1, 2, 3, 63, 64, 65, 255, 256, TILE - 1, TILE, TILE + 1, 3 * TILE + 17,
-         (1 << 15) + (1 << 14), 100003]
+TILE = 16384  # elements per tile of the digit-pass kernel (8192 for 64-bit pairs)
+# every path: one-workgroup LDS sorts (caps 4096 and 16384/8192), one tile,
+# several tiles with a ragged tail, the paper's 2^n + 2^(n-1) lengths
+SIZES = [1, 2, 3, 63, 64, 65, 255, 256, 4095, 4096, 4097, 8191, 8192, 8193, TILE - 1, TILE,
+         TILE + 1, 3 * TILE + 17, (1 << 15) + (1 << 14), 100003]
 
 
 @pytest.fixture(scope="module")
@@ -119,13 +121,14 @@ def test_full_size_u64(rs, oracle_lib, pairs, dist):
         assert np.array_equal(gv, ov)
 
 
+@pytest.mark.parametrize("n", [3000, 3 * TILE + 5])
 @pytest.mark.parametrize("bits", [32, 64])
 @pytest.mark.parametrize("mask_bits", [0, 8, 24, None])
 @pytest.mark.parametrize("pairs", [False, True])
-def test_in_place_and_skipped_passes(rs, oracle_lib, bits, mask_bits, pairs):
+def test_in_place_and_skipped_passes(rs, oracle_lib, n, bits, mask_bits, pairs):
     """In-place sorts with 0, 1, 3 and all moving passes (skipped passes
-    change which buffer the result lands in)."""
-    n = 3 * TILE + 5
+    change which buffer the result lands in), on the one-workgroup path and
+    the multi-tile path."""
     keys = datagen.keys("uniform", n, bits, seed=7)
     if mask_bits is not None:
         keys = keys & keys.dtype.type((1 << mask_bits) - 1)

@@ -272,3 +272,24 @@ def test_distribution_recipes():
     assert np.unique(b).size == 64
     assert (b >> np.uint64(32)).any()  # the high word is random too
     assert not datagen.keys("zero", n, 32).any()
+
+
+def test_segmented_certificate_has_teeth(oracle_lib):
+    from tests.certify import certify_segmented
+    sizes = [5, 0, 300, 2, 1000]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    total = int(off[-1])
+    keys = datagen.keys("bucket", total, 32, seed=8)
+    vals = (np.arange(total) - np.repeat(off[:-1], sizes)).astype(np.uint32)
+    k, v = oracle_lib.segmented_sort(keys, vals, off)
+    assert certify_segmented(keys, k, v, off) is None
+    # a sort across a segment boundary is caught
+    kk, vv = oracle_lib.sort(keys, np.arange(total, dtype=np.uint32))
+    assert certify_segmented(keys, kk, vv, off) is not None
+    # an unstable swap inside a segment is caught
+    a, b = int(off[4]), int(off[5])
+    i = a + int(np.nonzero(k[a + 1:b] == k[a:b - 1])[0][0])
+    k2, v2 = k.copy(), v.copy()
+    v2[[i, i + 1]] = v2[[i + 1, i]]
+    assert "unstable" in certify_segmented(keys, k2, v2, off)
