@@ -44,6 +44,7 @@ constexpr uint32_t kPlanCopyIn = 2u;       // no pass runs: copy in -> out here
 constexpr int kPlanSrcShift = 2;           // buffer id, 2 bits
 constexpr int kPlanDstShift = 4;           // buffer id, 2 bits
 constexpr uint32_t kBufIn = 0, kBufOut = 1, kBufTmp = 2;
+constexpr uint32_t kPlanBallot = 64u;      // skewed digit: rank with ballots, not the LDS table
 
 template <typename K>
 struct KeyTraits;

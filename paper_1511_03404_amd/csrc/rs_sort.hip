@@ -116,33 +116,26 @@ __device__ __forceinline__ void count_one(uint32_t (*sh)[kRadix], K key)
 }
 
 // Count a batch of NK keys per thread (a full batch: every lane active).
-// Runs of equal digits are common in skewed inputs (zero, sorted, bucket)
-// and same-address LDS atomics serialise, so per digit position: if the
-// whole wave holds one digit, one lane adds NK*64; if this thread's NK
-// digits are equal, it adds NK once; otherwise one atomic per key.
+// Key slot i of the wave covers 64 neighbouring vectors of the input, and in
+// skewed inputs (zero, sorted, reverse) a digit position is often the same
+// over the whole slot; same-address LDS atomics serialise (0.5 lanes/clock
+// against ~6 for spread addresses), so such a slot adds 64 once.
 template <typename K, int NK>
 __device__ __forceinline__ void count_batch(uint32_t (*sh)[kRadix], const K (&key)[NK])
 {
     constexpr int D = KeyTraits<K>::kBits / kRadixBits;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
-        uint32_t dg[NK];
-        bool eq = true;
 #pragma unroll
         for (int i = 0; i < NK; ++i) {
-            dg[i] = KeyTraits<K>::digit(key[i], p * kRadixBits);
-            eq = eq && dg[i] == dg[0];
-        }
-        const uint32_t first = __builtin_amdgcn_readfirstlane(dg[0]);
-        if (__ballot(!(eq && dg[0] == first)) == 0) {
-            if (lane_id() == 0)
-                atomicAdd(&sh[p][first], (uint32_t)(NK * kWave));
-        } else if (eq) {
-            atomicAdd(&sh[p][dg[0]], (uint32_t)NK);
-        } else {
-#pragma unroll
-            for (int i = 0; i < NK; ++i)
-                atomicAdd(&sh[p][dg[i]], 1u);
+            const uint32_t dg = KeyTraits<K>::digit(key[i], p * kRadixBits);
+            const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
+            if (__ballot(dg != first) == 0) {
+                if (lane_id() == 0)
+                    atomicAdd(&sh[p][first], (uint32_t)kWave);
+            } else {
+                atomicAdd(&sh[p][dg], 1u);
+            }
         }
     }
 }
@@ -235,14 +228,32 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
 {
     __shared__ uint32_t s_tmp[8];
     __shared__ int s_trivial[D];
+    __shared__ int s_skewed[D];
+    __shared__ unsigned long long s_sq[kRadix / kWave];
     const uint32_t t = threadIdx.x;
     for (int p = 0; p < D; ++p) {
         const uint32_t c = a.hist[p * kRadix + t];
         const uint32_t ex = block_exclusive_scan_256<kRadix>(c, s_tmp);
         a.digit_base[p * kRadix + t] = ex;
         const int triv = __syncthreads_or(c == a.n);
-        if (t == 0)
+        // chance that two keys share this digit: sum_b (c_b / n)^2
+        unsigned long long sq = (unsigned long long)c * c;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            sq += __shfl_xor(sq, off);
+        if ((t & (kWave - 1)) == 0)
+            s_sq[t / kWave] = sq;
+        __syncthreads();
+        if (t == 0) {
             s_trivial[p] = triv;
+            unsigned long long tot = 0;
+            for (int i = 0; i < kRadix / kWave; ++i)
+                tot += s_sq[i];
+            // above 1/100 many lanes of a wave share a slot of the LDS lane-mask
+            // table, whose same-address atomics serialise; ballots do not
+            s_skewed[p] = tot * 100ull > (unsigned long long)a.n * a.n;
+        }
+        __syncthreads();
     }
     __syncthreads();
     if (t == 0) {
@@ -260,7 +271,8 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
                     dst = (q & 1) ? kBufOut : kBufTmp;
                 else
                     dst = ((q_total - 1 - q) & 1) ? kBufTmp : kBufOut;
-                plan = kPlanRun | (prev << kPlanSrcShift) | (dst << kPlanDstShift);
+                plan = kPlanRun | (prev << kPlanSrcShift) | (dst << kPlanDstShift) |
+                       (s_skewed[p] ? kPlanBallot : 0u);
                 prev = dst;
                 ++q;
             }
@@ -352,20 +364,36 @@ __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
     }
 }
 
+// dst[lo, hi) = src[lo, hi), 16-byte vectors where both arrays allow it.
+template <typename T>
+__device__ __forceinline__ void copy_range(const T *src, T *dst, uint64_t lo, uint64_t hi,
+                                           uint32_t t, uint32_t threads)
+{
+    constexpr uint64_t E = 16 / sizeof(T);  // elements per vector
+    const bool vec = ((((uintptr_t)(src + lo)) | ((uintptr_t)(dst + lo))) & 15) == 0;
+    if (vec) {
+        const uint64_t nv = (hi - lo) / E;
+        const uint4 *s4 = (const uint4 *)(src + lo);
+        uint4 *d4 = (uint4 *)(dst + lo);
+        for (uint64_t i = t; i < nv; i += threads)
+            d4[i] = s4[i];
+        for (uint64_t i = lo + nv * E + t; i < hi; i += threads)
+            dst[i] = src[i];
+    } else {
+        for (uint64_t i = lo + t; i < hi; i += threads)
+            dst[i] = src[i];
+    }
+}
+
 template <typename K, typename V, bool HAS_V>
 __device__ __forceinline__ void copy_tile(const PassArgs &a, uint64_t lo, uint64_t hi,
                                           uint32_t t, uint32_t threads)
 {
-    const K *ik = pick<const K>(a.b, kBufIn, false);
-    K *ok = pick<K>(a.b, kBufOut, false);
-    for (uint64_t i = lo + t; i < hi; i += threads)
-        ok[i] = ik[i];
-    if constexpr (HAS_V) {
-        const V *iv = pick<const V>(a.b, kBufIn, true);
-        V *ov = pick<V>(a.b, kBufOut, true);
-        for (uint64_t i = lo + t; i < hi; i += threads)
-            ov[i] = iv[i];
-    }
+    copy_range(pick<const K>(a.b, kBufIn, false), pick<K>(a.b, kBufOut, false), lo, hi, t,
+               threads);
+    if constexpr (HAS_V)
+        copy_range(pick<const V>(a.b, kBufIn, true), pick<V>(a.b, kBufOut, true), lo, hi, t,
+                   threads);
 }
 
 // p[i] = v.  For 4-byte elements the byte offset fits in 32 bits (n < 2^30),
@@ -427,7 +455,7 @@ __device__ __forceinline__ void pass_tile(PassLds<K, V, THREADS, THREADS * ITEMS
                                           const K *tk, const V *tv, K *dk, V *dv,
                                           uint32_t valid, uint32_t limit, uint32_t tile,
                                           uint32_t first_tile, uint32_t *status, uint32_t dbase,
-                                          int shift)
+                                          int shift, bool ballot_rank)
 {
     constexpr int T = THREADS * ITEMS;
     constexpr int W = THREADS / kWave;
@@ -450,7 +478,7 @@ __device__ __forceinline__ void pass_tile(PassLds<K, V, THREADS, THREADS * ITEMS
 
     // count: stable rank of every item among the wave's items of its digit
     uint32_t rank[ITEMS];
-    if constexpr (LDS_MATCH) {
+    if (LDS_MATCH && !ballot_rank) {
         wave_rank<K, KeyTraits<K>, ITEMS>(key, shift, wc, s_mask + w * kRadix, lane, rank);
     } else {
 #pragma unroll
@@ -603,7 +631,7 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_pass(PassAr
         const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tb);
         pass_tile<K, V, HAS_V, THREADS, S::kItems, S::kLookback, S::kLdsMatch>(
             L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile, 0, a.status, dbase,
-            a.shift);
+            a.shift, (plan & kPlanBallot) != 0);
     }
 }
 
@@ -667,7 +695,7 @@ __global__ __launch_bounds__((PassShape<K, HAS_V>::kThreads)) void k_seg_pass(Se
         pass_tile<K, V, HAS_V, THREADS, S::kItems, S::kLookback, S::kLdsMatch>(
             L, (const K *)a.src_k + off, HAS_V ? (const V *)a.src_v + off : nullptr,
             (K *)a.dst_k + rec.start, HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
-            tile, rec.tile_start, a.status, dbase, a.shift);
+            tile, rec.tile_start, a.status, dbase, a.shift, false);
     }
 }
 
