@@ -111,14 +111,151 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="u32_pairs", choices=sorted(WORKLOADS) + ["copy_calib"])
+    ap.add_argument("--workload", default="u32_pairs",
+                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented"])
     ap.add_argument("--dists", default="all",
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="print the traffic summary of rocprofv3 --pmc runs under DIR and exit")
+    ap.add_argument("--segments", type=int, default=20000,
+                    help="segmented workload: number of segments")
+    ap.add_argument("--seg-log2", default="4,20",
+                    help="segmented workload: log2 of the smallest and largest segment size")
+    ap.add_argument("--per-segment-steps", type=int, default=1,
+                    help="segmented workload: timed steps of the one-sort-per-segment form")
     return ap.parse_args()
+
+
+def bench_segmented(args, torch, rs, datagen, dev):
+    """Batched segmented sort: S independent u32 key + u32 value sorts with
+    log-uniform sizes, as one enqueue (eager and replayed from a captured
+    HIP graph), against one sort call per segment on the same stream."""
+    lo, hi = (int(x) for x in args.seg_log2.split(","))
+    S = args.segments
+    t0 = time.perf_counter()
+    keys, vals, off = datagen.segmented(num_segments=S, lo_log2=lo, hi_log2=hi, bits=32, seed=1)
+    gen_s = time.perf_counter() - t0
+    total = int(off[-1])
+    sizes = np.diff(off.astype(np.int64))
+    kd = torch.from_numpy(keys).to(dev)
+    vd = torch.from_numpy(vals).to(dev)
+    offd = torch.from_numpy(off.view(np.int64)).to(dev)
+    ko = torch.empty_like(kd)
+    vo = torch.empty_like(vd)
+    ctx = rs.context(0)
+    ws = torch.empty(ctx.segmented_workspace_bytes(32, True, total, S), dtype=torch.uint8,
+                     device=dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def batched():
+        rs.segmented_sort(kd, vd, offd, ko, vo, ctx=ctx, workspace=ws)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    ev0.record()
+    for _ in range(args.steps):
+        batched()
+    ev1.record()
+    torch.cuda.synchronize()
+    ctx.profile_enable(False)
+    batched_ms = ev0.elapsed_time(ev1) / args.steps
+    recs = ctx.profile_read()
+    kern = {}
+    for name, tag, ms in recs:
+        kern.setdefault(name, []).append(ms)
+    kern_ms = {k: round(sum(v) / args.steps, 4) for k, v in kern.items()}
+
+    # the same enqueue captured once into a graph and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batched()
+    g.replay()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        g.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+
+    # one sort call per segment, same stream, no host synchronisation
+    ws1 = torch.empty(ctx.workspace_bytes(32, True, int(sizes.max())), dtype=torch.uint8,
+                      device=dev)
+    bounds = list(zip(off[:-1].tolist(), off[1:].tolist()))
+
+    def per_segment():
+        for a, b in bounds:
+            if b - a > 1:
+                rs.sort_pairs(kd[a:b], vd[a:b], ko[a:b], vo[a:b], ctx=ctx, workspace=ws1)
+            elif b - a == 1:
+                ko[a:b].copy_(kd[a:b])
+                vo[a:b].copy_(vd[a:b])
+
+    per_segment()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.per_segment_steps):
+        per_segment()
+    torch.cuda.synchronize()
+    per_seg_ms = (time.perf_counter() - t0) * 1e3 / args.per_segment_steps
+
+    large = sizes[sizes > 16384]
+    pass_ms = kern.get("k_seg_pass_u32", [])
+    roofline = None
+    if pass_ms:
+        avg = sum(pass_ms) / len(pass_ms)
+        bpl = 2 * int(large.sum()) * 8
+        achieved = bpl / (avg * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "k_seg_pass_u32", "avg_launch_ms": round(avg, 5),
+                    "launches": len(pass_ms), "bytes_per_launch": bpl,
+                    "elements_in_large_segments": int(large.sum())}
+    out = {
+        "metric": "Mkeys/s, batched segmented sort vs one launch per segment",
+        "value": round(total / batched_ms / 1e3, 1),
+        "unit": "Mkeys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(batched_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{S} independent u32 key + u32 value segments, sizes "
+                               f"floor(2^({lo}+{hi - lo}u)) log-uniform in [2^{lo}, 2^{hi}], "
+                               f"uniform keys, value = index in segment; MT19937 seed 1",
+                   "segments": S, "total_elements": total,
+                   "elements_in_large_segments": int(large.sum()),
+                   "segments_by_class": {"le1": int((sizes <= 1).sum()),
+                                         "small_le4096": int(((sizes > 1) & (sizes <= 4096)).sum()),
+                                         "medium_le16384": int(((sizes > 4096) & (sizes <= 16384)).sum()),
+                                         "large": int(large.size)}},
+        "batched_ms": round(batched_ms, 3),
+        "graph_replay_ms": round(graph_ms, 3),
+        "graph_replay_Mkeys_s": round(total / graph_ms / 1e3, 1),
+        "per_segment_launch_ms": round(per_seg_ms, 3),
+        "per_segment_launch_Mkeys_s": round(total / per_seg_ms / 1e3, 1),
+        "speedup_batched_vs_per_segment": round(per_seg_ms / batched_ms, 2),
+        "hbm_frac_whole_batch": round(4 * 2 * total * 8 / (batched_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "kernels_ms": kern_ms,
+        "roofline": roofline,
+        "host_generation_s": round(gen_s, 1),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        m = min(S, 200)
+        a, b = 0, int(off[m])
+        t0 = time.perf_counter()
+        oracle.segmented_sort(keys[a:b], vals[a:b], off[:m + 1])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round((b - a) / dt / 1e6, 3), "unit": "Mkeys/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"the first {m} segments ({b - a} elements), one thread, "
+                                         f"{dt:.1f} s"}
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(bits, has_v, dists, sample_log2):
@@ -175,6 +312,9 @@ def main():
         print(json.dumps({"workload": "copy_calib", "bytes_read": COPY_CALIB_BYTES,
                           "bytes_written": COPY_CALIB_BYTES,
                           "launches": args.warmup + args.steps}), flush=True)
+        return
+    if args.workload == "segmented":
+        bench_segmented(args, torch, rs, datagen, dev)
         return
     n, bits, has_v, wdesc = WORKLOADS[args.workload]
     dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")

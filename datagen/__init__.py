@@ -124,8 +124,11 @@ def segmented(num_segments: int = 20000, lo_log2: int = 4, hi_log2: int = 20,
     total = int(offsets[-1])
     k = _draw(g, bits, total)
     dt = np.uint32 if bits == 32 else np.uint64
-    v = np.arange(total, dtype=np.int64) - np.repeat(offsets[:-1].astype(np.int64), sizes)
-    return k, v.astype(dt), offsets
+    v = np.empty(total, dtype=dt)
+    ramp = np.arange(int(sizes.max()) if sizes.size else 0, dtype=dt)
+    for a, n in zip(offsets[:-1].tolist(), sizes.tolist()):
+        v[a:a + n] = ramp[:n]
+    return k, v, offsets
 
 
 def requests(num: int, rate_per_s: float, lo_log2: int = 10, hi_log2: int = 24,

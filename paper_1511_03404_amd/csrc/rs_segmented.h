@@ -29,7 +29,13 @@ constexpr int kSegMediumClaim = 5;
 constexpr int kSegHistClaim = 6;
 constexpr int kSegError = 7;        // bit 0: a segment of 2^30+ elements; bit 1: tiles overflow
 constexpr int kSegPassCounter = 8;  // [8, 16): group counter per pass
+constexpr int kSegChunks = 16;      // histogram chunks of the large segments
+constexpr int kSegChunkClaim = 17;
+constexpr int kSegScanClaim = 18;
 constexpr int kSegWords = 64;
+// Large segments are histogrammed in chunks of this many elements, so that
+// one huge segment does not leave a single workgroup reading it alone.
+constexpr uint32_t kSegChunk = 1u << 18;
 
 struct SegClassifyArgs {
     const uint64_t *offsets;
@@ -41,6 +47,8 @@ struct SegClassifyArgs {
     SegRange *medium_list;
     SegLarge *large;
     uint32_t *tile_seg;
+    uint32_t *chunk_seg;  // large segment of each histogram chunk
+    uint32_t max_chunks;
     const void *kin;
     const void *vin;
     void *kout;
@@ -84,18 +92,25 @@ __global__ __launch_bounds__(256) void k_seg_classify(SegClassifyArgs a)
             a.large[idx] = SegLarge{start, fits ? (uint32_t)size : 0u, ts};
             for (uint32_t i = 0; i < nt && ts + i < a.max_tiles; ++i)
                 a.tile_seg[ts + i] = idx;
+            const uint32_t nc = (uint32_t)((size + kSegChunk - 1) / kSegChunk);
+            const uint32_t cs = atomicAdd(&a.ctrl[kSegChunks], nc);
+            for (uint32_t i = 0; i < nc && cs + i < a.max_chunks; ++i)
+                a.chunk_seg[cs + i] = idx;
         }
     }
 }
 
-// Histograms of all digit positions of each large segment, then their
-// exclusive scans: seg_base[seg][p][b] = elements of the segment whose digit
-// p is below b.  Persistent workgroups claim segments.
+// Digit histograms of the large segments, chunk by chunk: persistent
+// workgroups claim chunks of kSegChunk elements, count all digit positions
+// in LDS and add the counts to the segment's histogram (global atomics).
 struct SegHistArgs {
     const void *kin;
     const SegLarge *large;
+    const uint32_t *chunk_seg;
+    uint32_t max_chunks;
     uint32_t *ctrl;
-    uint32_t *seg_base;
+    uint32_t *seg_hist;  // [large segment][d][256], zeroed
+    uint32_t *seg_base;  // [large segment][d][256]
 };
 
 template <typename K>
@@ -104,47 +119,79 @@ __global__ __launch_bounds__(256) void k_seg_hist(SegHistArgs a)
     constexpr int D = KeyTraits<K>::kBits / kRadixBits;
     constexpr int W = 256 / kWave;
     __shared__ uint32_t sh[W][D][kRadix];
-    __shared__ uint32_t s_tmp[8];
     __shared__ uint32_t s_item;
     const uint32_t t = threadIdx.x;
     const uint32_t w = t / kWave;
     const K *keys = (const K *)a.kin;
+    const uint32_t chunks = min(a.ctrl[kSegChunks], a.max_chunks);
     while (true) {
         if (t == 0)
-            s_item = atomicAdd(&a.ctrl[kSegHistClaim], 1u);
+            s_item = atomicAdd(&a.ctrl[kSegChunkClaim], 1u);
         for (int i = t; i < W * D * kRadix; i += 256)
             (&sh[0][0][0])[i] = 0;
         __syncthreads();
         const uint32_t item = s_item;
-        if (item >= a.ctrl[kSegLargeLen])
+        if (item >= chunks)
             break;
-        const SegLarge rec = a.large[item];
-        const K *sk = keys + rec.start;
-        for (uint32_t i = t; i < rec.size; i += 256) {
+        const uint32_t seg = a.chunk_seg[item];
+        const SegLarge rec = a.large[seg];
+        // this chunk's index within its segment: chunks of a segment are
+        // consecutive, so count back to the segment's first chunk
+        uint32_t first = item;
+        while (first > 0 && a.chunk_seg[first - 1] == seg)
+            --first;
+        const uint64_t lo = (uint64_t)(item - first) * kSegChunk;
+        const uint32_t len = rec.size > lo ? (uint32_t)min<uint64_t>(kSegChunk, rec.size - lo) : 0u;
+        const K *sk = keys + rec.start + lo;
+        for (uint32_t i = t; i < len; i += 256) {
             const K key = sk[i];
+            const uint64_t active = __ballot(1);  // before any branch narrows it
 #pragma unroll
             for (int p = 0; p < D; ++p) {
                 const uint32_t dg = KeyTraits<K>::digit(key, p * kRadixBits);
                 // a digit held by the whole wave is added once (same-address
                 // LDS atomics serialise)
-                const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
-                const uint64_t active = __ballot(1);  // before any branch narrows it
-                if (__ballot(dg != first) == 0) {
+                const uint32_t first_dg = __builtin_amdgcn_readfirstlane(dg);
+                if (__ballot(dg != first_dg) == 0) {
                     if (lane_id() == (uint32_t)__builtin_ctzll(active))
-                        atomicAdd(&sh[w][p][first], (uint32_t)__popcll(active));
+                        atomicAdd(&sh[w][p][first_dg], (uint32_t)__popcll(active));
                 } else {
                     atomicAdd(&sh[w][p][dg], 1u);
                 }
             }
         }
         __syncthreads();
-        uint32_t *out = a.seg_base + (uint64_t)item * D * kRadix;
-        for (int p = 0; p < D; ++p) {
+        uint32_t *out = a.seg_hist + (uint64_t)seg * D * kRadix;
+        for (int i = t; i < D * kRadix; i += 256) {
             uint32_t c = 0;
 #pragma unroll
             for (int ww = 0; ww < W; ++ww)
-                c += sh[ww][p][t];
-            out[p * kRadix + t] = block_exclusive_scan_256<256>(c, s_tmp);
+                c += (&sh[ww][0][0])[i];
+            if (c)
+                atomicAdd(&out[i], c);
+        }
+        __syncthreads();
+    }
+}
+
+// seg_base[seg][p] = exclusive scan of seg_hist[seg][p], one workgroup per
+// large segment (persistent).
+template <int D>
+__global__ __launch_bounds__(256) void k_seg_scan(SegHistArgs a)
+{
+    __shared__ uint32_t s_tmp[8];
+    __shared__ uint32_t s_item;
+    const uint32_t t = threadIdx.x;
+    while (true) {
+        if (t == 0)
+            s_item = atomicAdd(&a.ctrl[kSegScanClaim], 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= a.ctrl[kSegLargeLen])
+            break;
+        for (int p = 0; p < D; ++p) {
+            const uint64_t i = ((uint64_t)item * D + p) * kRadix + t;
+            a.seg_base[i] = block_exclusive_scan_256<256>(a.seg_hist[i], s_tmp);
         }
         __syncthreads();
     }

@@ -1073,8 +1073,10 @@ struct SegLayout {
     int d;
     uint64_t max_tiles;
     uint64_t claim_words;
+    uint64_t max_chunks;
     uint64_t off_ctrl, off_small, off_medium, off_large, off_base, off_tile_seg, off_status,
         status_bytes, off_tmp_k, off_tmp_v, total;
+    uint64_t off_hist, off_chunk_seg;
 };
 
 static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total, uint32_t nseg)
@@ -1101,8 +1103,14 @@ static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total,
     o = align_up(o + (uint64_t)nseg * L.d * kRadix * 4, 256);
     L.off_tile_seg = o;
     o = align_up(o + L.max_tiles * 4, 256);
+    L.max_chunks = total / kSegChunk + nseg + 1;
+    L.off_chunk_seg = o;
+    o = align_up(o + L.max_chunks * 4, 256);
+    // zeroed region: look-back words, claim counters, segment histograms
     L.off_status = o;
     L.status_bytes = align_up((uint64_t)L.d * (L.max_tiles * kRadix + L.claim_words) * 4, 16);
+    L.off_hist = L.off_status + L.status_bytes;
+    L.status_bytes += align_up((uint64_t)nseg * L.d * kRadix * 4, 16);
     o = align_up(o + L.status_bytes, 256);
     L.off_tmp_k = o;
     o = align_up(o + total * key_bytes, 256);
@@ -1169,6 +1177,8 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     SegLarge *large = (SegLarge *)(wb + L.off_large);
     uint32_t *seg_base = (uint32_t *)(wb + L.off_base);
     uint32_t *tile_seg = (uint32_t *)(wb + L.off_tile_seg);
+    uint32_t *chunk_seg = (uint32_t *)(wb + L.off_chunk_seg);
+    uint32_t *seg_hist = (uint32_t *)(wb + L.off_hist);
     uint32_t *status = (uint32_t *)(wb + L.off_status);
     void *tmp_k = wb + L.off_tmp_k;
     void *tmp_v = HAS_V ? (void *)(wb + L.off_tmp_v) : nullptr;
@@ -1186,8 +1196,8 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
         hipLaunchKernelGGL(k_zero, dim3(std::max(1u, g)), dim3(256), 0, s, (uint4 *)status, nvec);
     });
     SegClassifyArgs ca{offsets, nseg, total, (uint32_t)L.max_tiles, ctrl, small_list, medium_list,
-                       large, tile_seg, kin, vin, kout, vout, (uint32_t)B::kSmallCap,
-                       (uint32_t)B::kMediumCap, (uint32_t)S::kTile};
+                       large, tile_seg, chunk_seg, (uint32_t)L.max_chunks, kin, vin, kout, vout,
+                       (uint32_t)B::kSmallCap, (uint32_t)B::kMediumCap, (uint32_t)S::kTile};
     launch(ctx, s, "k_seg_classify", [&] {
         const uint32_t g = std::min<uint32_t>(1024, (nseg + 255) / 256);
         hipLaunchKernelGGL((k_seg_classify<K, HAS_V>), dim3(std::max(1u, g)), dim3(256), 0, s, ca);
@@ -1224,10 +1234,13 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     // large segments: per-segment histograms, then the batched digit passes,
     // in -> tmp -> out -> ... (an even number of passes ends in out)
     {
-        SegHistArgs ha{kin, large, ctrl, seg_base};
+        SegHistArgs ha{kin, large, chunk_seg, (uint32_t)L.max_chunks, ctrl, seg_hist, seg_base};
         auto kern = k_seg_hist<K>;
-        const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, 256), nseg);
+        const uint32_t g = std::min<uint64_t>(grid_of((const void *)kern, 256), L.max_chunks);
         launch(ctx, s, "k_seg_hist", [&] { hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, ha); });
+        auto scan = k_seg_scan<KeyTraits<K>::kBits / kRadixBits>;
+        const uint32_t gs = std::min<uint32_t>(grid_of((const void *)scan, 256), nseg);
+        launch(ctx, s, "k_seg_scan", [&] { hipLaunchKernelGGL(scan, dim3(gs), dim3(256), 0, s, ha); });
     }
     {
         auto kern = k_seg_pass<K, K, HAS_V>;
