@@ -112,7 +112,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="u32_pairs",
-                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented"])
+                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented", "serving"])
     ap.add_argument("--dists", default="all",
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -125,7 +125,77 @@ def parse():
                     help="segmented workload: log2 of the smallest and largest segment size")
     ap.add_argument("--per-segment-steps", type=int, default=1,
                     help="segmented workload: timed steps of the one-sort-per-segment form")
+    ap.add_argument("--requests", type=int, default=100000,
+                    help="serving workload: number of requests per load level")
+    ap.add_argument("--slots", type=int, default=4, help="serving workload: streams")
     return ap.parse_args()
+
+
+def bench_serving(args, torch, rs, datagen, dev):
+    """Serving loop: Poisson arrivals of sort requests (sizes log-uniform in
+    [2^10, 2^24], half 32-bit and half 64-bit keys, half with values), device
+    buffers capped at 64 GB, continuous batching on several streams.  The
+    saturation rate R_max comes from a closed-loop run (all requests queued
+    at once); open-loop runs at 0.5 and 0.9 R_max report p50/p99 latency."""
+    from paper_1511_03404_amd.serving import HipBackend, Request, Scheduler, serve, summarize
+    lo, hi = 10, 24
+    # inputs resident in HBM: request keys are slices of a random pool, values
+    # slices of an index ramp (value = index within the request)
+    pool = torch.from_numpy(datagen.MT19937(1).u64((1 << hi) + (1 << 22))).to(dev)
+    idx = torch.arange(1 << hi, dtype=torch.int64, device=dev)
+    ramp = {32: idx.to(torch.uint32), 64: idx.to(torch.uint64)}
+
+    def requests(rate):
+        out = []
+        for q in datagen.requests(args.requests, rate_per_s=rate, lo_log2=lo, hi_log2=hi, seed=1):
+            n, bits = q["n"], q["bits"]
+            src = pool.view(torch.uint32) if bits == 32 else pool
+            off = q["key_seed"] % (src.numel() - n)
+            vals = ramp[bits][:n] if q["has_values"] else None
+            out.append(Request(q["id"], n, bits, q["has_values"], q["arrival_s"],
+                               payload=(src[off:off + n], vals)))
+        return out
+
+    def run(reqs, open_loop):
+        be = HipBackend(slots=args.slots, keep_results=False)
+        sch = Scheduler(be, mem_cap=64 << 30, slots=args.slots, max_batch_elems=1 << 25)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        be.mark_clock_zero(0.0)
+        done = serve(sch, reqs, lambda: time.perf_counter() - t0, open_loop=open_loop)
+        torch.cuda.synchronize()
+        makespan = max(r.done_s for r in done)
+        st = summarize(done, makespan)
+        st.update({"failed": len(sch.failed), "rejected": len(sch.rejected),
+                   "peak_inflight_batches": sch.peak_inflight,
+                   "peak_admitted_GB": round(sch.peak_mem / 1e9, 2)})
+        return st
+
+    # warm-up on a few requests, then the closed loop for R_max
+    run(requests(1e6)[:64], open_loop=False)
+    closed = run(requests(1e6), open_loop=False)
+    r_max = closed["requests"] / closed["makespan_s"]
+    levels = {}
+    for frac in (0.5, 0.9):
+        levels[str(frac)] = run(requests(frac * r_max), open_loop=True)
+        levels[str(frac)]["rate_req_s"] = round(frac * r_max, 1)
+    main = levels["0.9"]
+    out = {
+        "metric": "Mkeys/s and p50/p99 latency, serving loop with continuous batching",
+        "value": main["Mkeys_s"], "unit": "Mkeys/s",
+        "n_gpus": 1, "steps": args.requests, "warmup": 64,
+        "ms_per_step": round(main["makespan_s"] * 1e3 / max(1, main["requests"]), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32+u64", "data": "synthetic",
+        "config": {"workload": f"{args.requests} Poisson-arriving sort requests, n = "
+                               f"floor(2^({lo}+{hi - lo}u)), half u32 / half u64 keys, half "
+                               f"key-value; 64 GB admission cap; {args.slots} streams; "
+                               f"rate 0.9 R_max", "requests": args.requests},
+        "r_max_req_s": round(r_max, 1),
+        "closed_loop": closed,
+        "open_loop": levels,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_segmented(args, torch, rs, datagen, dev):
@@ -315,6 +385,9 @@ def main():
         return
     if args.workload == "segmented":
         bench_segmented(args, torch, rs, datagen, dev)
+        return
+    if args.workload == "serving":
+        bench_serving(args, torch, rs, datagen, dev)
         return
     n, bits, has_v, wdesc = WORKLOADS[args.workload]
     dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")
