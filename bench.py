@@ -35,14 +35,18 @@ COPY_CALIB_BYTES = 1 << 30  # plain copy used to calibrate the HBM byte counters
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("paper_1511_03404_amd/csrc/rs_sort.hip", "paper_1511_03404_amd/csrc/rs_device.h")
+# the sources of the digit-pass kernel: counter readings taken on other
+# sources are stale
+KERNEL_SOURCES = ("paper_1511_03404_amd/csrc/rs_kernels.h", "paper_1511_03404_amd/csrc/rs_device.h",
+                  "paper_1511_03404_amd/csrc/rs_segmented.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-PASS_KERNEL = {
-    "u32_pairs": "void rs::k_pass<unsigned int, unsigned int, true>",
-    "u64_keys": "void rs::k_pass<unsigned long, unsigned long, false>",
-    "u64_pairs": "void rs::k_pass<unsigned long, unsigned long, true>",
-    "u32_keys_small": "void rs::k_pass<unsigned int, unsigned int, false>",
-}
+
+
+def pass_kernel_name(bits, has_v, cfg):
+    """The digit-pass kernel's name as rocprofv3 prints it (without arguments)."""
+    t = "unsigned int" if bits == 32 else "unsigned long"
+    return (f"void rs::k_pass<{t}, {t}, {'true' if has_v else 'false'}, "
+            f"rs::PassCfg<{cfg['radix_bits']}, {cfg['threads']}, {cfg['items']}> >")
 
 
 def kernel_source_hash() -> str:
@@ -54,9 +58,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, cfg):
     """HBM bytes per digit-pass launch from the committed counter summary,
-    or None if it is missing or was taken on a different kernel source."""
+    or None if it is missing, was taken on a different kernel source or on
+    another configuration."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -65,7 +70,9 @@ def measured_traffic(workload):
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     w = t.get("workloads", {}).get(workload)
-    return None if w is None else w.get("traffic_bytes_per_launch")
+    if w is None or w.get("config") != cfg:
+        return None
+    return w.get("traffic_bytes_per_launch")
 
 
 def summarize_pmc(root):
@@ -92,14 +99,17 @@ def summarize_pmc(root):
            "calibration": f"1 GiB plain copy (torch copy_, runtime blit kernel): FETCH_SIZE "
                           f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB",
            "workloads": {}}
-    for w, k in PASS_KERNEL.items():
+    import paper_1511_03404_amd as rs
+    for w, (_, bits, has_v, _) in WORKLOADS.items():
+        cfg = rs.configs(bits, has_v)[0]  # the counter runs use the default configuration
+        k = pass_kernel_name(bits, has_v, cfg)
         fp = os.path.join(root, w, "FETCH_SIZE", "run_counter_collection.csv")
         wp = os.path.join(root, w, "WRITE_SIZE", "run_counter_collection.csv")
         if not (os.path.exists(fp) and os.path.exists(wp)):
             continue
         f, nf = mean(fp, k)
         wr, _ = mean(wp, k)
-        out["workloads"][w] = {"kernel": k, "fetch_kib_per_launch": round(f, 1),
+        out["workloads"][w] = {"kernel": k, "config": cfg, "fetch_kib_per_launch": round(f, 1),
                                "write_kib_per_launch": round(wr, 1),
                                "traffic_bytes_per_launch": int(f * 1024 * fs + wr * 1024 * ws),
                                "launches_sampled": nf}
@@ -116,6 +126,8 @@ def parse():
     ap.add_argument("--dists", default="all",
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: use the default configuration (index 0)")
     ap.add_argument("--cpu-sample-log2", type=int, default=24)
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="print the traffic summary of rocprofv3 --pmc runs under DIR and exit")
@@ -175,10 +187,12 @@ def bench_serving(args, torch, rs, datagen, dev):
     run(requests(1e6)[:64], open_loop=False)
     closed = run(requests(1e6), open_loop=False)
     r_max = closed["requests"] / closed["makespan_s"]
+    print(f"closed loop: {closed}", file=sys.stderr, flush=True)
     levels = {}
     for frac in (0.5, 0.9):
         levels[str(frac)] = run(requests(frac * r_max), open_loop=True)
         levels[str(frac)]["rate_req_s"] = round(frac * r_max, 1)
+        print(f"open loop {frac} R_max: {levels[str(frac)]}", file=sys.stderr, flush=True)
     main = levels["0.9"]
     out = {
         "metric": "Mkeys/s and p50/p99 latency, serving loop with continuous batching",
@@ -215,6 +229,15 @@ def bench_segmented(args, torch, rs, datagen, dev):
     ko = torch.empty_like(kd)
     vo = torch.empty_like(vd)
     ctx = rs.context(0)
+    tuning = None
+    if not args.no_tune:
+        # the autotuner times every configuration on this batch and selects
+        # the fastest; the eager runs and the captured graph below use it
+        from paper_1511_03404_amd import tune
+        tuning = tune.tune_segmented(kd, vd, offd, ctx=ctx, reps=3, warmup=1)
+        print(f"tuned: {tuning}", file=sys.stderr, flush=True)
+    cfg_index = ctx.tune_get(32, True, True, rs.size_class(total))
+    cfg = rs.configs(32, True)[cfg_index]
     ws = torch.empty(ctx.segmented_workspace_bytes(32, True, total, S), dtype=torch.uint8,
                      device=dev)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -312,6 +335,8 @@ def bench_segmented(args, torch, rs, datagen, dev):
         "hbm_frac_whole_batch": round(4 * 2 * total * 8 / (batched_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "kernels_ms": kern_ms,
         "roofline": roofline,
+        "kernel_config": dict(cfg, index=cfg_index),
+        "tuning": tuning,
         "host_generation_s": round(gen_s, 1),
     }
     if not args.no_cpu_baseline:
@@ -403,6 +428,15 @@ def main():
     ko = torch.empty(n, dtype=ins[0][1].dtype, device=dev)
     vo = torch.empty(n, dtype=ins[0][1].dtype, device=dev) if has_v else None
     ctx = rs.context(0)
+    tuning = None
+    if not args.no_tune:
+        # the autotuner times every compiled configuration on uniform keys of
+        # this size and selects the fastest for the size class (untimed)
+        from paper_1511_03404_amd import tune
+        tuning = tune.tune_sort(bits, has_v, n, ctx=ctx, reps=5, warmup=1)
+        print(f"tuned: {tuning}", file=sys.stderr, flush=True)
+    cfg_index = ctx.tune_get(bits, has_v, False, rs.size_class(n))
+    cfg = rs.configs(bits, has_v)[cfg_index]
     ws = torch.empty(ctx.workspace_bytes(bits, has_v, n), dtype=torch.uint8, device=dev)
 
     def step():
@@ -460,8 +494,9 @@ def main():
         achieved = bytes_per_launch / (avg * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(args.workload),
-                    "kernel": pass_name, "avg_launch_ms": round(avg, 5),
+                    "traffic": measured_traffic(args.workload, cfg),
+                    "kernel": pass_name, "kernel_instance": pass_kernel_name(bits, has_v, cfg),
+                    "avg_launch_ms": round(avg, 5),
                     "launches": len(pass_ms), "bytes_per_launch": bytes_per_launch,
                     "input": dists[ref]}
 
@@ -482,7 +517,10 @@ def main():
         "config": {"workload": f"{wdesc}; one sort per distribution per step "
                                f"({', '.join(dists)}); MT19937 seed 1",
                    "n": n, "key_bits": bits, "value_bits": bits if has_v else 0,
-                   "distributions": dists, "digit_bits": 8},
+                   "distributions": dists, "digit_bits": cfg["radix_bits"],
+                   "tile": f"{cfg['threads']}x{cfg['items']}"},
+        "kernel_config": dict(cfg, index=cfg_index),
+        "tuning": tuning,
         "hbm_frac_whole_sort": round(whole_frac, 4),
         "roofline": roofline,
         "per_distribution": per,

@@ -77,8 +77,10 @@ void rs_context_destroy(rs_context *ctx);
 
 /*
  * Bytes of scratch memory one sort of n elements needs (look-back words,
- * digit histograms, one ping-pong copy of the keys and values).  Pure host
- * arithmetic; never touches the device.
+ * digit histograms, one ping-pong copy of the keys and values) with the
+ * configuration the context's tune table selects for n (see rs_tune_set:
+ * query again after changing the table).  Pure host arithmetic; never
+ * touches the device.
  */
 rs_status rs_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int has_values,
                              uint64_t n, size_t *bytes);
@@ -91,7 +93,7 @@ rs_status rs_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int ha
 rs_status rs_sort_keys_u32(rs_context *ctx, const uint32_t *keys_in, uint32_t *keys_out,
                            uint64_t n, void *ws, size_t ws_bytes, void *stream);
 
-/* As rs_sort_keys_u32 for 64-bit keys (8 digit passes of 8 bits). */
+/* As rs_sort_keys_u32 for 64-bit keys. */
 rs_status rs_sort_keys_u64(rs_context *ctx, const uint64_t *keys_in, uint64_t *keys_out,
                            uint64_t n, void *ws, size_t ws_bytes, void *stream);
 
@@ -125,7 +127,8 @@ rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *k
                             void *ws, size_t ws_bytes, void *stream);
 
 /* Scratch bytes for rs_segmented_sort on `total` elements in num_segments
- * segments.  Pure host arithmetic. */
+ * segments, with the configuration the tune table selects for `total`.
+ * Pure host arithmetic. */
 rs_status rs_segmented_workspace_bytes(const rs_context *ctx, rs_key_type key_type,
                                        int has_values, uint64_t total, uint32_t num_segments,
                                        size_t *bytes);
@@ -153,6 +156,49 @@ rs_status rs_profile_reset(rs_context *ctx);
  */
 rs_status rs_profile_read(rs_context *ctx, const char **names, int *tags, float *ms, int max,
                           int *count);
+
+/*
+ * Kernel configurations and the tune table.
+ *
+ * The digit width r is a free parameter of the method (Section 2.6: the
+ * keys are cut into r-bit digits and sorted with one counting sort per
+ * digit; the result does not depend on r).  The library is compiled for a
+ * fixed list of configurations per key type and values/no values: r of 4 to
+ * 8 bits (ceil(key bits / r) digit passes) and tile shapes of threads x
+ * items elements per workgroup.  Index 0 of each list is the default.  Each
+ * context holds a tune table that picks one configuration per key type,
+ * values or not, plain or segmented sort, and size class ceil(log2 n) (n of
+ * the plain sort, `total` of the segmented one).  Sorts that fit one
+ * workgroup's LDS (up to 16384 elements, 8192 for 64-bit pairs) and the
+ * small and medium segments always use the one-workgroup sort, whatever the
+ * table says.  Every configuration gives the same, bit-exact result.
+ */
+typedef struct rs_config {
+    int radix_bits; /* digit width r, 4..8 */
+    int threads;    /* workgroup size of the digit pass */
+    int items;      /* elements per thread; a tile holds threads * items */
+} rs_config;
+
+/* Number of compiled configurations for this key type, with/without values. */
+rs_status rs_config_count(rs_key_type key_type, int has_values, int *count);
+
+/* Configuration `index` (0 <= index < count) of that list. */
+rs_status rs_config_get(rs_key_type key_type, int has_values, int index, rs_config *config);
+
+/*
+ * Select configuration `index` (-1 = the default) for sorts of this kind
+ * whose size class ceil(log2 n) is size_log2 (0..39), or for every size
+ * class if size_log2 is -1.  segmented != 0 selects the table of
+ * rs_segmented_sort.  Takes effect for calls enqueued afterwards; a
+ * workspace sized before the change may be too small for the new choice
+ * (the sort then returns RS_ERR_INVALID_ARGUMENT).
+ */
+rs_status rs_tune_set(rs_context *ctx, rs_key_type key_type, int has_values, int segmented,
+                      int size_log2, int index);
+
+/* The configuration index the table selects for one size class (0..39). */
+rs_status rs_tune_get(const rs_context *ctx, rs_key_type key_type, int has_values, int segmented,
+                      int size_log2, int *index);
 
 /* Static description of a status code. */
 const char *rs_status_string(rs_status status);

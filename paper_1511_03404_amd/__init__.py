@@ -28,13 +28,25 @@ RS_ERR_DEVICE = 4
 RS_KEY_U32 = 0
 RS_KEY_U64 = 1
 MAX_ELEMENTS = 1 << 30
+# sorts up to this many elements run in one workgroup's LDS (one launch),
+# whatever configuration the tune table selects
+BLOCK_SORT_CAP = {(32, False): 16384, (32, True): 16384, (64, False): 16384, (64, True): 8192}
 
 EXPORTED = (
     "rs_context_create", "rs_context_destroy", "rs_workspace_bytes",
     "rs_sort_keys_u32", "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
     "rs_segmented_sort", "rs_segmented_workspace_bytes", "rs_status_string", "rs_last_error",
     "rs_profile_enable", "rs_profile_tag", "rs_profile_reset", "rs_profile_read",
+    "rs_config_count", "rs_config_get", "rs_tune_set", "rs_tune_get",
 )
+
+
+class Config(ctypes.Structure):
+    """``rs_config``: digit width and tile shape of the digit passes."""
+    _fields_ = [("radix_bits", ctypes.c_int), ("threads", ctypes.c_int), ("items", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"radix_bits": self.radix_bits, "threads": self.threads, "items": self.items}
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -78,11 +90,16 @@ def lib():
                                           ci, ctypes.POINTER(ci)]
             L.rs_last_error.argtypes = []
             L.rs_last_error.restype = ctypes.c_char_p
+            L.rs_config_count.argtypes = [ci, ci, ctypes.POINTER(ci)]
+            L.rs_config_get.argtypes = [ci, ci, ci, ctypes.POINTER(Config)]
+            L.rs_tune_set.argtypes = [vp, ci, ci, ci, ci, ci]
+            L.rs_tune_get.argtypes = [vp, ci, ci, ci, ci, ctypes.POINTER(ci)]
             for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
                          "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
                          "rs_segmented_sort", "rs_segmented_workspace_bytes",
                          "rs_profile_enable", "rs_profile_tag", "rs_profile_reset",
-                         "rs_profile_read"):
+                         "rs_profile_read", "rs_config_count", "rs_config_get",
+                         "rs_tune_set", "rs_tune_get"):
                 getattr(L, name).restype = ci
             _lib = L
     return _lib
@@ -130,6 +147,21 @@ class Context:
                                                   num_segments, ctypes.byref(out)))
         return out.value
 
+    # -- tune table (configuration per kind and size class) --------------
+    def tune_set(self, key_bits: int, has_values: bool, segmented: bool, size_log2: int,
+                 index: int):
+        """Use configuration ``index`` (-1: the default) for sorts of this kind
+        with ceil(log2 n) == size_log2 (-1: every size)."""
+        kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
+        _check(lib().rs_tune_set(self.handle, kt, int(has_values), int(segmented),
+                                 int(size_log2), int(index)))
+
+    def tune_get(self, key_bits: int, has_values: bool, segmented: bool, size_log2: int) -> int:
+        kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
+        out = ctypes.c_int()
+        _check(lib().rs_tune_get(self.handle, kt, int(has_values), int(segmented),
+                                 int(size_log2), ctypes.byref(out)))
+        return out.value
 
     # -- per-kernel timing (HIP events around each launch) ---------------
     def profile_enable(self, on: bool = True):
@@ -153,6 +185,25 @@ class Context:
         ms = (ctypes.c_float * m)()
         _check(lib().rs_profile_read(self.handle, names, tags, ms, m, ctypes.byref(count)))
         return [(names[i].decode(), tags[i], ms[i]) for i in range(m)]
+
+
+def configs(key_bits: int, has_values: bool) -> list[dict]:
+    """The compiled digit-pass configurations for this kind, in index order
+    (index 0 is the default)."""
+    kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
+    n = ctypes.c_int()
+    _check(lib().rs_config_count(kt, int(has_values), ctypes.byref(n)))
+    out = []
+    for i in range(n.value):
+        c = Config()
+        _check(lib().rs_config_get(kt, int(has_values), i, ctypes.byref(c)))
+        out.append(c.as_dict())
+    return out
+
+
+def size_class(n: int) -> int:
+    """ceil(log2 n): the tune table's size class of a sort of n elements."""
+    return max(0, int(n - 1).bit_length()) if n > 1 else 0
 
 
 _contexts: dict[int, Context] = {}

@@ -10,14 +10,17 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librs.so")
-SOURCES = ["rs_sort.hip"]
+# rs_sort.hip: host logic and the configuration-independent kernels; the
+# rs_var_* units instantiate the digit-pass kernels of every configuration.
+SOURCES = ["rs_sort.hip", "rs_var_u32.hip", "rs_var_u64.hip", "rs_var_u32_seg.hip",
+           "rs_var_u64_seg.hip"]
+OBJ_DIR = os.path.join(PKG, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -31,19 +34,40 @@ def hipcc() -> str:
     return exe
 
 
+def _errors(res) -> str:
+    return "\n".join(l for l in (res.stderr or "").splitlines() if "packed-fp32-ops" not in l)
+
+
 def build(verbose: bool = False) -> str:
+    """Compile every unit (in parallel) and link librs.so in the package."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJ_DIR, src.replace(".hip", ".o"))
+        cmd = [hipcc(), *HIPCC_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                stderr=subprocess.PIPE, text=True)))
+    failed = []
+    for src, obj, proc in jobs:
+        out, err = proc.communicate()
+        res = subprocess.CompletedProcess(proc.args, proc.returncode, out, err)
+        if proc.returncode != 0:
+            failed.append(f"{src}:\n{_errors(res)}")
+        elif verbose and _errors(res).strip():
+            print(_errors(res), file=sys.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC",
+           *[o for _, o, _ in jobs], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    errs = "\n".join(l for l in (res.stderr or "").splitlines()
-                     if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + errs)
-    if verbose and errs.strip():
-        print(errs, file=sys.stderr)
+        raise RuntimeError("link failed:\n" + _errors(res))
     os.replace(tmp, LIB)
     return LIB
 

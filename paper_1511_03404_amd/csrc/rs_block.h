@@ -47,7 +47,7 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
 {
     constexpr int CAP = THREADS * ITEMS;
     constexpr int W = THREADS / kWave;
-    constexpr int D = KeyTraits<K>::kBits / kRadixBits;
+    constexpr int D = num_passes<K, kRadixBits>();
     constexpr size_t kStageBytes = (size_t)CAP * (sizeof(K) + (HAS_V ? sizeof(V) : 0));
     static_assert((size_t)W * kRadix * 8 <= kStageBytes, "mask table lives in the staging buffer");
 
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
             }
             __syncthreads();
             uint32_t rank[ITEMS];
-            wave_rank<K, KeyTraits<K>, ITEMS>(key, shift, wc, s_mask + w * kRadix, lane, rank);
+            wave_rank<kRadixBits, K, ITEMS>(key, shift, wc, s_mask + w * kRadix, lane, rank);
             __syncthreads();
             // exclusive offsets over (digit, wave): digit-major, so that
             // earlier waves (earlier elements) come first within a digit
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
                     cnt += c;
                 }
             }
-            const uint32_t excl = block_exclusive_scan_256<THREADS>(cnt, s_tmp);
+            const uint32_t excl = bins_exclusive_scan<kRadix>(cnt, s_tmp);
             if (t < kRadix) {
 #pragma unroll
                 for (int ww = 0; ww < W; ++ww)
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
-                const uint32_t pos = rank[j] + wc[KeyTraits<K>::digit(key[j], shift)];
+                const uint32_t pos = rank[j] + wc[digit_of<kRadixBits>(key[j], shift)];
                 s_k[pos] = key[j];
                 if constexpr (HAS_V)
                     s_v[pos] = val[j];

@@ -4,12 +4,14 @@
 // (Section 2.6): count the digits, exclusive-scan the counts, place every
 // element at its digit's running offset in input order.  On the GPU the
 // three steps are spread over a tile of T elements per workgroup:
-//   * count  -- a wave64 "multisplit": eight ballots give each lane the mask
-//               of lanes holding the same digit; the lowest such lane adds
-//               the group size to a per-wave LDS counter, and the rank inside
-//               the group is mbcnt over the mask.  Items are visited in input
-//               order (wave-striped: item j of lane l is element j*64 + l of
-//               the wave's run), which is what makes the ranking stable;
+//   * count  -- a wave64 "multisplit": each lane learns the mask of lanes
+//               holding the same digit (from a per-wave LDS table of lane
+//               masks, or from one ballot per digit bit when the digits are
+//               skewed); the lowest such lane adds the group size to a
+//               per-wave LDS counter, and the rank inside the group is mbcnt
+//               over the mask.  Items are visited in input order
+//               (wave-striped: item j of lane l is element j*64 + l of the
+//               wave's run), which is what makes the ranking stable;
 //   * scan   -- digit_base (global exclusive scan of the digit histogram) +
 //               a decoupled look-back over the tiles before this one +
 //               the tile-local exclusive scan over digits and waves;
@@ -22,9 +24,13 @@
 
 namespace rs {
 
+// Digit widths R of 4..8 bits are compiled; a pass has 2^R bins.  kRadix is
+// the largest bin count (sizes of LDS tables shared by all widths, the
+// 256-thread scans) and kRadixBits the default width.
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kWave = 64;
+constexpr int kMaxPasses = 16;  // 64-bit keys at 4-bit digits
 
 // Look-back status word: [31:30] flag, [29:0] digit count.
 constexpr uint32_t kFlagAgg = 1u << 30;  // count of this tile only
@@ -33,9 +39,9 @@ constexpr uint32_t kFlagMask = 3u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1;
 
 // Control block (u32 words at the start of the workspace).
-constexpr int kCtrlTileCounter = 0;  // [0, 8): dynamic tile id per pass
-constexpr int kCtrlPlan = 16;        // [16, 24): plan word per pass
-constexpr int kCtrlFinal = 32;       // final copy: 0 none, 1 tmp -> out
+constexpr int kCtrlTileCounter = 0;  // [0, 16): dynamic tile id per pass
+constexpr int kCtrlPlan = 16;        // [16, 32): plan word per pass
+constexpr int kCtrlFinal = 48;       // final copy: 0 none, 1 tmp -> out
 constexpr int kCtrlWords = 64;
 
 // Plan word of one pass.
@@ -53,22 +59,43 @@ template <>
 struct KeyTraits<uint32_t> {
     static constexpr int kBits = 32;
     static constexpr uint32_t kPad = 0xFFFFFFFFu;
-    __device__ static __forceinline__ uint32_t digit(uint32_t k, int shift)
-    {
-        return __builtin_amdgcn_ubfe(k, (uint32_t)shift, (uint32_t)kRadixBits);
-    }
 };
 
 template <>
 struct KeyTraits<uint64_t> {
     static constexpr int kBits = 64;
     static constexpr uint64_t kPad = ~0ull;
-    __device__ static __forceinline__ uint32_t digit(uint64_t k, int shift)
-    {
-        uint32_t w = shift < 32 ? (uint32_t)k : (uint32_t)(k >> 32);
-        return __builtin_amdgcn_ubfe(w, (uint32_t)(shift & 31), (uint32_t)kRadixBits);
-    }
 };
+
+// Number of R-bit digit positions of a K key (the last one may be narrower).
+template <typename K, int R>
+constexpr int num_passes()
+{
+    return (KeyTraits<K>::kBits + R - 1) / R;
+}
+
+// The R-bit digit of k that starts at bit `shift` (bits above the key's top
+// read as zero, so the last, narrower digit is exact too).
+template <int R>
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift)
+{
+    if constexpr (32 % R == 0)
+        return __builtin_amdgcn_ubfe(k, (uint32_t)shift, (uint32_t)R);
+    else
+        return (k >> shift) & ((1u << R) - 1u);
+}
+
+template <int R>
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift)
+{
+    if constexpr (32 % R == 0) {
+        // the digit lies within one 32-bit half
+        const uint32_t w = shift < 32 ? (uint32_t)k : (uint32_t)(k >> 32);
+        return __builtin_amdgcn_ubfe(w, (uint32_t)(shift & 31), (uint32_t)R);
+    } else {
+        return (uint32_t)(k >> shift) & ((1u << R) - 1u);
+    }
+}
 
 __device__ __forceinline__ uint32_t lane_id()
 {
@@ -82,16 +109,17 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Mask of the lanes of this (full) wave whose 8-bit digit equals ours.
+// Mask of the lanes of this (full) wave whose R-bit digit equals ours.
 // For every bit b: s = 0 or ~0 (our bit, sign-extended), bal = the wave's
 // ballot of that bit; bal ^ s marks the lanes whose bit b differs from ours.
-// OR-ing those over the 8 bits (one 3-input v_bitop3 per half: a | (b ^ c))
+// OR-ing those over the R bits (one 3-input v_bitop3 per half: a | (b ^ c))
 // leaves exactly the equal lanes clear.
+template <int R>
 __device__ __forceinline__ uint64_t peer_mask(uint32_t d)
 {
     uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < R; ++b) {
         const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);
         const uint64_t bal = __ballot(s != 0);
         diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)bal, s, 0xF6);
@@ -118,23 +146,26 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
     return v;
 }
 
-// Exclusive scan of one value per thread over the first 256 threads of the
-// block (4 waves).  `tmp` is 4 words of LDS.  Must be called by every thread
-// of the block (barriers inside); threads >= 256 get 0.
-template <int THREADS>
-__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *tmp)
+// Exclusive scan of one value per thread over the first max(NB, 64) threads
+// of the block (NB <= 256: one value per digit bin; threads past NB must pass
+// 0).  `tmp` is 4 words of LDS.  Must be called by every thread of the block
+// (barriers inside); threads past the scanned ones get 0.
+template <int NB>
+__device__ __forceinline__ uint32_t bins_exclusive_scan(uint32_t v, uint32_t *tmp)
 {
+    static_assert(NB <= kRadix, "at most 256 bins");
+    constexpr uint32_t kT = NB < kWave ? kWave : NB;
     const uint32_t t = threadIdx.x;
     const uint32_t w = t / kWave;
     uint32_t inc = 0;
-    if (t < kRadix) {
+    if (t < kT) {
         inc = wave_inclusive_scan(v);
         if ((t & (kWave - 1)) == kWave - 1)
             tmp[w] = inc;
     }
     __syncthreads();
     uint32_t excl = 0;
-    if (t < kRadix) {
+    if (t < kT) {
         uint32_t before = 0;
         for (uint32_t i = 0; i < w; ++i)
             before += tmp[i];
@@ -145,23 +176,23 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
 }
 
 // Stable rank of ITEMS keys per lane among the keys of this wave that share
-// their digit.  Items are visited j = 0..ITEMS-1 and, within an item, by lane,
-// which must be the input order of the wave's elements.  wc is the wave's
-// 256-entry running count per digit (zeroed by the caller); wm a 256-entry
-// table of 64-bit lane masks (zeroed by the caller, left zeroed).  For every
-// item each lane ORs its bit into its digit's slot and reads the slot back:
-// that is the mask of lanes holding the same digit.  The group's lowest lane
-// advances the count and clears the slot.  rank = count before the group +
-// lanes of the group below this one.  After the call wc holds the wave's
-// total per digit.
-template <typename K, typename Traits, int ITEMS>
+// their R-bit digit.  Items are visited j = 0..ITEMS-1 and, within an item,
+// by lane, which must be the input order of the wave's elements.  wc is the
+// wave's 2^R-entry running count per digit (zeroed by the caller); wm a
+// 2^R-entry table of 64-bit lane masks (zeroed by the caller, left zeroed).
+// For every item each lane ORs its bit into its digit's slot and reads the
+// slot back: that is the mask of lanes holding the same digit.  The group's
+// lowest lane advances the count and clears the slot.  rank = count before
+// the group + lanes of the group below this one.  After the call wc holds
+// the wave's total per digit.
+template <int R, typename K, int ITEMS>
 __device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], int shift, uint32_t *wc,
                                           uint64_t *wm, uint32_t lane, uint32_t (&rank)[ITEMS])
 {
     const uint64_t lane_bit = 1ull << lane;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t d = Traits::digit(key[j], shift);
+        const uint32_t d = digit_of<R>(key[j], shift);
         atomicOr(&wm[d], lane_bit);
         const uint64_t m = wm[d];
         const uint32_t c = wc[d];

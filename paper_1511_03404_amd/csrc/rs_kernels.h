@@ -1,0 +1,815 @@
+// Digit-pass kernels of the LSD radix sort, templated on the configuration
+// (digit width R, tile shape THREADS x ITEMS).
+//
+// Method (paper, Section 2.6): d = ceil(K/R) passes of R-bit digits, least
+// significant first, each a stable counting sort.  The GPU realisation:
+//
+//   k_hist     one read of the keys -> histograms of all d digit positions;
+//              also clears the look-back words of every pass
+//   k_plan     one workgroup: scans each histogram row into digit_base (the
+//              counting sort's exclusive prefix sums) and writes a plan:
+//              which passes move data (a pass whose histogram has a single
+//              non-empty digit is the identity and is skipped) and which
+//              buffer each pass reads and writes
+//   k_pass     one per digit position: a single sweep over the data that
+//              counts, scans (decoupled look-back across tiles) and places
+//              each tile; see rs_device.h.
+//   k_seg_hist / k_seg_scan / k_seg_pass
+//              the same for the large segments of a segmented sort, every
+//              segment with its own histograms and look-back chain.
+#pragma once
+
+#include <algorithm>
+
+#include "rs_device.h"
+#include "rs_segmented.h"
+
+namespace rs {
+
+// Consecutive tiles claimed as a group (see claim_tile).
+constexpr int kClaimGroup = 8;
+
+// Configuration of the digit passes.
+//   kLookback  predecessor tiles read per look-back round trip
+//   kGroup     consecutive tiles claimed as a group (see claim_tile)
+// Keys are staged in LDS, written out, then the values go through the same
+// buffer; the per-wave lane-mask table is only live while ranking and shares
+// it too.  Big tiles amortise the per-tile latencies (tile claim, look-back)
+// and make the digit runs of the scatter longer.
+template <int R, int THREADS, int ITEMS>
+struct PassCfg {
+    static_assert(R >= 4 && R <= 8, "digit widths of 4..8 bits");
+    static_assert(THREADS % kWave == 0 && THREADS >= 256 && THREADS <= 1024, "256..1024 threads");
+    static constexpr int kRadixBits = R;
+    static constexpr int kBins = 1 << R;
+    static constexpr int kThreads = THREADS;
+    static constexpr int kItems = ITEMS;
+    static constexpr int kTile = THREADS * ITEMS;
+    static constexpr int kLookback = 8;
+    static constexpr int kGroup = kClaimGroup;
+};
+
+constexpr int kHistThreads = 256;
+
+struct Bufs {
+    const void *in_k;
+    const void *in_v;
+    void *out_k;
+    void *out_v;
+    void *tmp_k;
+    void *tmp_v;
+};
+
+template <typename T>
+__device__ __forceinline__ T *pick(const Bufs &b, uint32_t id, bool values)
+{
+    const void *p = values ? (id == kBufIn ? b.in_v : id == kBufOut ? b.out_v : b.tmp_v)
+                           : (id == kBufIn ? b.in_k : id == kBufOut ? b.out_k : b.tmp_k);
+    return (T *)p;
+}
+
+// ---------------------------------------------------------------------------
+// k_hist: all-digit histograms in one read of the keys; also clears the
+// look-back words of every pass.
+
+struct HistArgs {
+    const void *keys;
+    uint32_t n;
+    uint32_t head;        // leading keys before the first 16-byte boundary
+    uint32_t nvec;        // 16-byte vectors after the head
+    uint32_t *hist;       // [d][2^R]
+    uint4 *status;        // look-back words of all passes, cleared here
+    uint64_t status_vec;  // number of uint4 in status
+};
+
+// Count one key's D digits into the wave's LDS sub-histograms.
+template <typename K, int R>
+__device__ __forceinline__ void count_one(uint32_t (*sh)[1 << R], K key)
+{
+    constexpr int D = num_passes<K, R>();
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+        atomicAdd(&sh[p][digit_of<R>(key, p * R)], 1u);
+}
+
+// Count a batch of NK keys per thread (a full batch: every lane active).
+// Key slot i of the wave covers 64 neighbouring vectors of the input, and in
+// skewed inputs (zero, sorted, reverse) a digit position is often the same
+// over the whole slot; same-address LDS atomics serialise (0.5 lanes/clock
+// against ~6 for spread addresses), so such a slot adds 64 once.
+template <typename K, int R, int NK>
+__device__ __forceinline__ void count_batch(uint32_t (*sh)[1 << R], const K (&key)[NK])
+{
+    constexpr int D = num_passes<K, R>();
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+#pragma unroll
+        for (int i = 0; i < NK; ++i) {
+            const uint32_t dg = digit_of<R>(key[i], p * R);
+            const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
+            if (__ballot(dg != first) == 0) {
+                if (lane_id() == 0)
+                    atomicAdd(&sh[p][first], (uint32_t)kWave);
+            } else {
+                atomicAdd(&sh[p][dg], 1u);
+            }
+        }
+    }
+}
+
+template <typename K, int R>
+__global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
+{
+    constexpr int D = num_passes<K, R>();
+    constexpr int NB = 1 << R;
+    constexpr int W = kHistThreads / kWave;
+    constexpr int KPV = 16 / (int)sizeof(K);  // keys per 16-byte vector
+    constexpr int VPT = 16 / KPV;             // vectors per thread per batch
+    constexpr int NK = VPT * KPV;             // 16 keys per thread per batch
+    constexpr uint32_t BATCH = kHistThreads * VPT;
+    __shared__ uint32_t sh[W][D][NB];
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t / kWave;
+    for (int i = t; i < W * D * NB; i += kHistThreads)
+        (&sh[0][0][0])[i] = 0;
+
+    // clear the look-back words of every pass
+    const uint64_t gtid = (uint64_t)blockIdx.x * kHistThreads + t;
+    const uint64_t gstride = (uint64_t)gridDim.x * kHistThreads;
+    for (uint64_t i = gtid; i < a.status_vec; i += gstride)
+        a.status[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+
+    const K *keys = (const K *)a.keys;
+    const uint4 *vec = (const uint4 *)(keys + a.head);
+    const uint64_t full_batches = a.nvec / BATCH;
+    for (uint64_t b = blockIdx.x; b < full_batches; b += gridDim.x) {
+        // vector v of this thread: b*BATCH + v*THREADS + t (each wave load is 1 KB contiguous)
+        uint4 v[VPT];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i)
+            v[i] = vec[b * BATCH + (uint64_t)i * kHistThreads + t];
+        K key[NK];
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            if constexpr (KPV == 4) {
+                key[4 * i + 0] = (K)v[i].x;
+                key[4 * i + 1] = (K)v[i].y;
+                key[4 * i + 2] = (K)v[i].z;
+                key[4 * i + 3] = (K)v[i].w;
+            } else {
+                key[2 * i + 0] = (K)(((uint64_t)v[i].y << 32) | v[i].x);
+                key[2 * i + 1] = (K)(((uint64_t)v[i].w << 32) | v[i].z);
+            }
+        }
+        count_batch<K, R, NK>(sh[w], key);
+    }
+    // the rest: unaligned head, vectors after the last full batch, ragged
+    // tail -- element by element, spread over the whole grid
+    const uint64_t rest0 = (uint64_t)a.head + full_batches * BATCH * KPV;
+    const uint64_t extra = a.head + (a.n - rest0);
+    for (uint64_t i = gtid; i < extra; i += gstride) {
+        const uint64_t idx = i < a.head ? i : rest0 + (i - a.head);
+        count_one<K, R>(sh[w], keys[idx]);
+    }
+    __syncthreads();
+
+    for (int i = t; i < D * NB; i += kHistThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww)
+            s += (&sh[ww][0][0])[i];
+        if (s)
+            atomicAdd(&a.hist[i], s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_plan (one workgroup of 256 threads): digit_base = exclusive scan of each
+// histogram row (the counting sort's starting offsets), and the plan of
+// every pass.  A pass whose digit is the same for all n keys is the identity
+// permutation and is skipped; the remaining passes alternate between the
+// output and the scratch copy so that the last one lands in the output.
+
+struct PlanArgs {
+    const uint32_t *hist;
+    uint32_t *digit_base;
+    uint32_t *ctrl;
+    uint32_t n;
+    int in_place;
+};
+
+template <typename K, int R>
+__global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
+{
+    constexpr int D = num_passes<K, R>();
+    constexpr int NB = 1 << R;
+    __shared__ uint32_t s_tmp[8];
+    __shared__ int s_trivial[D];
+    __shared__ int s_skewed[D];
+    __shared__ unsigned long long s_sq[kRadix / kWave];
+    const uint32_t t = threadIdx.x;
+    for (int p = 0; p < D; ++p) {
+        const uint32_t c = t < (uint32_t)NB ? a.hist[p * NB + t] : 0u;
+        const uint32_t ex = bins_exclusive_scan<NB>(c, s_tmp);
+        if (t < (uint32_t)NB)
+            a.digit_base[p * NB + t] = ex;
+        const int triv = __syncthreads_or(c == a.n);
+        // chance that two keys share this digit: sum_b (c_b / n)^2
+        unsigned long long sq = (unsigned long long)c * c;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            sq += __shfl_xor(sq, off);
+        if ((t & (kWave - 1)) == 0)
+            s_sq[t / kWave] = sq;
+        __syncthreads();
+        if (t == 0) {
+            s_trivial[p] = triv;
+            unsigned long long tot = 0;
+            for (int i = 0; i < kRadix / kWave; ++i)
+                tot += s_sq[i];
+            // above 1/100 many lanes of a wave share a slot of the LDS lane-mask
+            // table, whose same-address atomics serialise; ballots do not
+            s_skewed[p] = tot * 100ull > (unsigned long long)a.n * a.n;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (t == 0) {
+        int q_total = 0;
+        for (int p = 0; p < D; ++p)
+            q_total += !s_trivial[p];
+        const bool odd_in_place = a.in_place && (q_total & 1);
+        int q = 0;
+        uint32_t prev = kBufIn;
+        for (int p = 0; p < D; ++p) {
+            uint32_t plan = 0;
+            if (!s_trivial[p]) {
+                uint32_t dst;
+                if (odd_in_place)
+                    dst = (q & 1) ? kBufOut : kBufTmp;
+                else
+                    dst = ((q_total - 1 - q) & 1) ? kBufTmp : kBufOut;
+                plan = kPlanRun | (prev << kPlanSrcShift) | (dst << kPlanDstShift) |
+                       (s_skewed[p] ? kPlanBallot : 0u);
+                prev = dst;
+                ++q;
+            }
+            a.ctrl[kCtrlPlan + p] = plan;
+        }
+        if (q_total == 0 && !a.in_place)
+            a.ctrl[kCtrlPlan + D - 1] = kPlanCopyIn;
+        a.ctrl[kCtrlFinal] = odd_in_place ? 1u : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_pass: one digit pass in a single sweep.
+
+struct PassArgs {
+    Bufs b;
+    uint32_t n;
+    int pass;
+    int shift;
+    uint32_t *ctrl;
+    const uint32_t *digit_base;  // row of this pass
+    uint32_t *status;            // [tiles][2^R] of this pass
+    uint32_t *claims;            // per-XCD claim counters and group lists
+    uint32_t num_tiles;
+    uint32_t num_groups;
+};
+
+// Which compute die (XCD) this wave runs on, from the XCC_ID hardware register.
+__device__ __forceinline__ uint32_t xcc_id()
+{
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 7u;
+}
+
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+
+// Claim the next tile for this workgroup (called by one thread).
+//
+// The digit runs of consecutive tiles meet inside shared cache lines.  When
+// the two tiles run on different XCDs, each XCD's L2 writes back a partial
+// line, which costs far more than one full line.  So consecutive tiles are
+// handed out in groups of GROUP, and the tiles of a group go to workgroups of
+// one XCD that start at about the same time:
+//   * every XCD keeps its own claim counter; claim k on XCD x takes tile
+//     k % GROUP of the XCD's group number k / GROUP;
+//   * the claim with k % GROUP == 0 opens that group: it takes the next group
+//     from the global counter and publishes the group's id in the XCD's
+//     list; the other claims of the same group wait for that id (the opener
+//     is running, so the wait is short).
+// Groups are opened in global order and the tiles of one XCD's groups
+// increase with its claim counter, so the lowest unfinished tile is always
+// held or next to be claimed by a running workgroup of its XCD (workgroups
+// keep claiming until the groups run out): the look-back waits cannot
+// depend on a workgroup that has not started.
+//
+// claims layout: [0, 8) per-XCD claim counters, then [8 + x*G + j] the id+1
+// of group j of XCD x (0 = not yet published, kNoTile = no group left).
+template <int GROUP>
+__device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
+{
+    uint32_t *ctr = &a.ctrl[kCtrlTileCounter + a.pass];
+    if constexpr (GROUP == 1) {
+        (void)xcc;
+        const uint32_t t = atomicAdd(ctr, 1u);
+        return t < a.num_tiles ? t : kNoTile;
+    } else {
+        uint32_t *list = a.claims + 8 + (uint64_t)xcc * a.num_groups;
+        while (true) {
+            const uint32_t k = atomicAdd(&a.claims[xcc], 1u);
+            const uint32_t j = k / GROUP, i = k % GROUP;
+            if (j >= a.num_groups)
+                return kNoTile;
+            uint32_t v;
+            if (i == 0) {
+                const uint32_t g = atomicAdd(ctr, 1u);
+                v = g < a.num_groups ? g + 1 : kNoTile;
+                __hip_atomic_store(&list[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                while ((v = __hip_atomic_load(&list[j], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                    __builtin_amdgcn_s_sleep(1);
+            }
+            if (v == kNoTile)
+                return kNoTile;
+            const uint32_t t = (v - 1) * GROUP + i;
+            if (t < a.num_tiles)
+                return t;
+            // past the end of a short last group: claim again
+        }
+    }
+}
+
+// dst[lo, hi) = src[lo, hi), 16-byte vectors where both arrays allow it.
+template <typename T>
+__device__ __forceinline__ void copy_range(const T *src, T *dst, uint64_t lo, uint64_t hi,
+                                           uint32_t t, uint32_t threads)
+{
+    constexpr uint64_t E = 16 / sizeof(T);  // elements per vector
+    const bool vec = ((((uintptr_t)(src + lo)) | ((uintptr_t)(dst + lo))) & 15) == 0;
+    if (vec) {
+        const uint64_t nv = (hi - lo) / E;
+        const uint4 *s4 = (const uint4 *)(src + lo);
+        uint4 *d4 = (uint4 *)(dst + lo);
+        for (uint64_t i = t; i < nv; i += threads)
+            d4[i] = s4[i];
+        for (uint64_t i = lo + nv * E + t; i < hi; i += threads)
+            dst[i] = src[i];
+    } else {
+        for (uint64_t i = lo + t; i < hi; i += threads)
+            dst[i] = src[i];
+    }
+}
+
+// p[i] = v.  For 4-byte elements the byte offset fits in 32 bits (n < 2^30),
+// which lets the store use a scalar base and a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ void store_at(T *p, uint32_t i, T v)
+{
+    if constexpr (sizeof(T) == 4)
+        *(T *)((char *)p + (i << 2)) = v;
+    else
+        p[i] = v;
+}
+
+template <typename K, typename V, bool HAS_V, int ITEMS>
+__device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t valid, uint32_t off0,
+                                          K (&key)[ITEMS], V (&val)[HAS_V ? ITEMS : 1], bool full)
+{
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            key[j] = tk[off0 + j * kWave];
+        if constexpr (HAS_V) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                val[j] = tv[off0 + j * kWave];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            key[j] = off0 + j * kWave < valid ? tk[off0 + j * kWave] : KeyTraits<K>::kPad;
+        if constexpr (HAS_V) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                val[j] = off0 + j * kWave < valid ? tv[off0 + j * kWave] : (V)0;
+        }
+    }
+}
+
+// LDS of one digit pass.
+template <typename K, typename C>
+struct PassLds {
+    static constexpr int W = C::kThreads / kWave;
+    static constexpr size_t kStageBytes = (size_t)C::kTile * sizeof(K);
+    static_assert((size_t)W * C::kBins * 8 <= kStageBytes,
+                  "the lane-mask tables live in the staging buffer");
+    uint32_t wcnt[W * C::kBins];  // per wave and digit: count, then base in tile
+    uint32_t gbase[C::kBins];
+    uint32_t tmp[8];
+    uint32_t tile;
+    __attribute__((aligned(16))) unsigned char stage[kStageBytes];
+
+    // zero the counters and the lane-mask tables before a tile
+    __device__ __forceinline__ void clear(uint32_t t)
+    {
+        for (int i = t; i < W * C::kBins; i += C::kThreads) {
+            wcnt[i] = 0;
+            ((uint64_t *)stage)[i] = 0;
+        }
+    }
+};
+
+// One tile of a digit pass (the paper's counting sort, Section 2.6, spread
+// over workgroups): rank, publish the tile's digit counts, decoupled
+// look-back over tiles [first_tile, tile), stage in LDS, write the digit
+// runs.  The tile's elements are tk/tv[0, valid); destination index i of the
+// digit-sorted sequence is dk/dv[i] for i < limit.  dbase (threads < 2^R) is
+// the digit's starting offset in that sequence.  Ends with a barrier.
+template <typename K, typename V, bool HAS_V, typename C>
+__device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V *tv, K *dk,
+                                          V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
+                                          uint32_t first_tile, uint32_t *status, uint32_t dbase,
+                                          int shift, bool ballot_rank)
+{
+    constexpr int R = C::kRadixBits;
+    constexpr uint32_t NB = C::kBins;
+    constexpr int THREADS = C::kThreads;
+    constexpr int ITEMS = C::kItems;
+    constexpr int T = C::kTile;
+    constexpr int W = THREADS / kWave;
+    constexpr int LBW = C::kLookback;
+    static_assert(sizeof(V) == sizeof(K), "values have the key's width");
+    K *s_k = (K *)L.stage;
+    V *s_v = (V *)L.stage;
+    uint64_t *s_mask = (uint64_t *)L.stage;
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t / kWave;
+    const uint32_t lane = t % kWave;
+    const uint32_t off0 = w * (kWave * ITEMS) + lane;
+    uint32_t *wc = L.wcnt + w * NB;
+
+    // load: item j of lane l is element j*64 + l of this wave's run
+    K key[ITEMS];
+    V val[HAS_V ? ITEMS : 1];
+    load_tile<K, V, HAS_V, ITEMS>(tk, tv, valid, off0, key, val, valid == (uint32_t)T);
+
+    // count: stable rank of every item among the wave's items of its digit
+    uint32_t rank[ITEMS];
+    if (!ballot_rank) {
+        wave_rank<R, K, ITEMS>(key, shift, wc, s_mask + w * NB, lane, rank);
+    } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t d = digit_of<R>(key[j], shift);
+            const uint64_t m = peer_mask<R>(d);
+            const uint32_t below = lanes_below(m);
+            const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+            uint32_t old = 0;
+            if (below == 0)
+                old = atomicAdd(&wc[d], (uint32_t)__popcll(m));
+            old = shfl_idx(old, leader);
+            rank[j] = old + below;
+        }
+    }
+    __syncthreads();
+
+    // scan: wave offsets per digit, tile count, publish the aggregate,
+    // tile-local offsets
+    uint32_t cnt = 0;
+    if (t < NB) {
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = L.wcnt[ww * NB + t];
+            L.wcnt[ww * NB + t] = cnt;
+            cnt += c;
+        }
+        __hip_atomic_store(&status[(uint64_t)tile * NB + t],
+                           (tile == first_tile ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t excl = bins_exclusive_scan<NB>(cnt, L.tmp);
+    if (t < NB) {
+        // decoupled look-back: read LBW predecessors per round trip, add
+        // their counts in order up to the first inclusive one; on a tile
+        // that has not published yet, wait and re-read from there
+        uint32_t prefix = 0;
+        int64_t k = (int64_t)tile - 1;
+        const int64_t lo = first_tile;
+        while (k >= lo) {
+            uint32_t st[LBW];
+#pragma unroll
+            for (int i = 0; i < LBW; ++i)
+                st[i] = (k - i >= lo)
+                            ? __hip_atomic_load(&status[(uint64_t)(k - i) * NB + t],
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : kFlagInc;
+            int used = 0;
+            bool done = false;
+#pragma unroll
+            for (int i = 0; i < LBW; ++i) {
+                if (!done && used == i) {
+                    const uint32_t f = st[i] & kFlagMask;
+                    if (f != 0) {
+                        prefix += st[i] & kCountMask;
+                        done = f == kFlagInc;
+                        used = i + 1;
+                    }
+                }
+            }
+            if (done)
+                break;
+            k -= used;
+            if (used < LBW)
+                __builtin_amdgcn_s_sleep(1);
+        }
+        if (tile != first_tile)
+            __hip_atomic_store(&status[(uint64_t)tile * NB + t], kFlagInc | (prefix + cnt),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        L.gbase[t] = dbase + prefix - excl;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww)
+            L.wcnt[ww * NB + t] += excl;
+    }
+    __syncthreads();
+
+    // place: stage the keys in rank order, then write each digit run out
+    // with consecutive lanes on consecutive addresses; then the values
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        rank[j] += wc[digit_of<R>(key[j], shift)];  // position in the tile
+        s_k[rank[j]] = key[j];
+    }
+    __syncthreads();
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t pos = i * THREADS + t;
+        const K k = s_k[pos];
+        dst[i] = L.gbase[digit_of<R>(k, shift)] + pos;
+        if (dst[i] < limit)
+            store_at(dk, dst[i], k);
+    }
+    if constexpr (HAS_V) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            s_v[rank[j]] = val[j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (dst[i] < limit)
+                store_at(dv, dst[i], s_v[i * THREADS + t]);
+    }
+    __syncthreads();  // LDS is reused by the next tile
+}
+
+template <typename K, typename V, bool HAS_V, typename C>
+__global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
+{
+    constexpr int THREADS = C::kThreads;
+    constexpr int T = C::kTile;
+    __shared__ PassLds<K, C> L;
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
+    if (!(plan & kPlanRun)) {
+        if (plan & kPlanCopyIn) {
+            // no pass moves data: copy in -> out
+            for (uint64_t tl = blockIdx.x; tl < a.num_tiles; tl += gridDim.x) {
+                const uint64_t lo = tl * T;
+                const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
+                copy_range(pick<const K>(a.b, kBufIn, false), pick<K>(a.b, kBufOut, false), lo,
+                           hi, t, THREADS);
+                if constexpr (HAS_V)
+                    copy_range(pick<const V>(a.b, kBufIn, true), pick<V>(a.b, kBufOut, true), lo,
+                               hi, t, THREADS);
+            }
+        }
+        return;
+    }
+    const uint32_t src = (plan >> kPlanSrcShift) & 3u;
+    const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
+    const K *sk = pick<const K>(a.b, src, false);
+    const V *sv = HAS_V ? pick<const V>(a.b, src, true) : nullptr;
+    K *dk = pick<K>(a.b, dstb, false);
+    V *dv = HAS_V ? pick<V>(a.b, dstb, true) : nullptr;
+    // this digit's starting offset, fetched early (used after the look-back)
+    const uint32_t dbase = t < (uint32_t)C::kBins ? a.digit_base[t] : 0u;
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    while (true) {
+        if (t == 0)
+            L.tile = claim_tile<C::kGroup>(a, xcc);
+        L.clear(t);
+        __syncthreads();
+        const uint32_t tile = L.tile;
+        if (tile == kNoTile)
+            break;
+        const uint64_t tb = (uint64_t)tile * T;
+        const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tb);
+        pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile,
+                                  0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segmented sort: digit histograms of the large segments, chunk by chunk.
+// Persistent workgroups claim chunks of kSegChunk elements, count all digit
+// positions in LDS and add the counts to the segment's histogram (global
+// atomics).
+
+struct SegHistArgs {
+    const void *kin;
+    const SegLarge *large;
+    const uint32_t *chunk_seg;
+    uint32_t max_chunks;
+    uint32_t *ctrl;
+    uint32_t *seg_hist;  // [large segment][d][2^R], zeroed
+    uint32_t *seg_base;  // [large segment][d][2^R]
+};
+
+template <typename K, int R>
+__global__ __launch_bounds__(256) void k_seg_hist(SegHistArgs a)
+{
+    constexpr int D = num_passes<K, R>();
+    constexpr int NB = 1 << R;
+    constexpr int W = 256 / kWave;
+    __shared__ uint32_t sh[W][D][NB];
+    __shared__ uint32_t s_item;
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t / kWave;
+    const K *keys = (const K *)a.kin;
+    const uint32_t chunks = min(a.ctrl[kSegChunks], a.max_chunks);
+    while (true) {
+        if (t == 0)
+            s_item = atomicAdd(&a.ctrl[kSegChunkClaim], 1u);
+        for (int i = t; i < W * D * NB; i += 256)
+            (&sh[0][0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= chunks)
+            break;
+        const uint32_t seg = a.chunk_seg[item];
+        const SegLarge rec = a.large[seg];
+        // this chunk's index within its segment: chunks of a segment are
+        // consecutive, so count back to the segment's first chunk
+        uint32_t first = item;
+        while (first > 0 && a.chunk_seg[first - 1] == seg)
+            --first;
+        const uint64_t lo = (uint64_t)(item - first) * kSegChunk;
+        const uint32_t len = rec.size > lo ? (uint32_t)min<uint64_t>(kSegChunk, rec.size - lo) : 0u;
+        const K *sk = keys + rec.start + lo;
+        for (uint32_t i = t; i < len; i += 256) {
+            const K key = sk[i];
+            const uint64_t active = __ballot(1);  // before any branch narrows it
+#pragma unroll
+            for (int p = 0; p < D; ++p) {
+                const uint32_t dg = digit_of<R>(key, p * R);
+                // a digit held by the whole wave is added once (same-address
+                // LDS atomics serialise)
+                const uint32_t first_dg = __builtin_amdgcn_readfirstlane(dg);
+                if (__ballot(dg != first_dg) == 0) {
+                    if (lane_id() == (uint32_t)__builtin_ctzll(active))
+                        atomicAdd(&sh[w][p][first_dg], (uint32_t)__popcll(active));
+                } else {
+                    atomicAdd(&sh[w][p][dg], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t *out = a.seg_hist + (uint64_t)seg * D * NB;
+        for (int i = t; i < D * NB; i += 256) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww)
+                c += (&sh[ww][0][0])[i];
+            if (c)
+                atomicAdd(&out[i], c);
+        }
+        __syncthreads();
+    }
+}
+
+// seg_base[seg][p] = exclusive scan of seg_hist[seg][p], one workgroup per
+// large segment (persistent).
+template <typename K, int R>
+__global__ __launch_bounds__(256) void k_seg_scan(SegHistArgs a)
+{
+    constexpr int D = num_passes<K, R>();
+    constexpr int NB = 1 << R;
+    __shared__ uint32_t s_tmp[8];
+    __shared__ uint32_t s_item;
+    const uint32_t t = threadIdx.x;
+    while (true) {
+        if (t == 0)
+            s_item = atomicAdd(&a.ctrl[kSegScanClaim], 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= a.ctrl[kSegLargeLen])
+            break;
+        for (int p = 0; p < D; ++p) {
+            const uint64_t i = ((uint64_t)item * D + p) * NB + t;
+            const uint32_t c = t < (uint32_t)NB ? a.seg_hist[i] : 0u;
+            const uint32_t ex = bins_exclusive_scan<NB>(c, s_tmp);
+            if (t < (uint32_t)NB)
+                a.seg_base[i] = ex;
+        }
+        __syncthreads();
+    }
+}
+
+// k_seg_pass: one digit pass over the tiles of every large segment.  Each
+// segment's tiles are consecutive in the batched tile sequence and its
+// look-back chain starts at its first tile.
+
+struct SegPassArgs {
+    const void *src_k;
+    const void *src_v;
+    void *dst_k;
+    void *dst_v;
+    const SegLarge *large;
+    const uint32_t *tile_seg;
+    const uint32_t *seg_base;  // [large segment][d][2^R]
+    uint32_t *ctrl;            // segmented control block
+    uint32_t *status;          // look-back words of this pass
+    uint32_t *claims;          // claim counters of this pass
+    uint32_t max_tiles;        // tiles the workspace holds
+    int pass;
+    int shift;
+    int d;
+};
+
+template <typename K, typename V, bool HAS_V, typename C>
+__global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
+{
+    constexpr int T = C::kTile;
+    constexpr uint32_t NB = C::kBins;
+    __shared__ PassLds<K, C> L;
+    const uint32_t t = threadIdx.x;
+    PassArgs pa{};
+    pa.ctrl = a.ctrl + (kSegPassCounter - kCtrlTileCounter);
+    pa.pass = a.pass;
+    pa.claims = a.claims;
+    pa.num_tiles = std::min(a.ctrl[kSegTiles], a.max_tiles);
+    pa.num_groups = (pa.num_tiles + C::kGroup - 1) / C::kGroup;
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    while (true) {
+        if (t == 0)
+            L.tile = claim_tile<C::kGroup>(pa, xcc);
+        L.clear(t);
+        __syncthreads();
+        const uint32_t tile = L.tile;
+        if (tile == kNoTile)
+            break;
+        const uint32_t seg = a.tile_seg[tile];
+        const SegLarge rec = a.large[seg];
+        const uint32_t lt = tile - rec.tile_start;
+        const uint32_t first = lt * T;
+        const uint32_t valid = rec.size > first ? std::min<uint32_t>(T, rec.size - first) : 0u;
+        const uint32_t dbase = t < NB ? a.seg_base[((uint64_t)seg * a.d + a.pass) * NB + t] : 0u;
+        const uint64_t off = rec.start + (uint64_t)lt * T;
+        pass_tile<K, V, HAS_V, C>(L, (const K *)a.src_k + off,
+                                  HAS_V ? (const V *)a.src_v + off : nullptr,
+                                  (K *)a.dst_k + rec.start,
+                                  HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
+                                  tile, rec.tile_start, a.status, dbase, a.shift, false);
+    }
+}
+
+// In-place segmented sort with an odd number of passes: the large segments
+// end in the scratch copy; copy them back, tile by tile.
+struct SegCopyArgs {
+    const void *src_k;
+    const void *src_v;
+    void *dst_k;
+    void *dst_v;
+    const SegLarge *large;
+    const uint32_t *tile_seg;
+    const uint32_t *ctrl;  // segmented control block
+    uint32_t max_tiles;
+    uint32_t tile;  // elements per tile
+};
+
+template <typename K, bool HAS_V>
+__global__ __launch_bounds__(256) void k_seg_copy(SegCopyArgs a)
+{
+    const uint32_t tiles = std::min(a.ctrl[kSegTiles], a.max_tiles);
+    for (uint32_t tl = blockIdx.x; tl < tiles; tl += gridDim.x) {
+        const SegLarge rec = a.large[a.tile_seg[tl]];
+        const uint64_t lo = (uint64_t)(tl - rec.tile_start) * a.tile;
+        if (lo >= rec.size)
+            continue;
+        const uint64_t hi = std::min<uint64_t>(lo + a.tile, rec.size);
+        copy_range((const K *)a.src_k + rec.start, (K *)a.dst_k + rec.start, lo, hi, threadIdx.x,
+                   256);
+        if constexpr (HAS_V)
+            copy_range((const K *)a.src_v + rec.start, (K *)a.dst_v + rec.start, lo, hi,
+                       threadIdx.x, 256);
+    }
+}
+
+}  // namespace rs

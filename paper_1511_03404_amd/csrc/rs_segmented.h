@@ -6,12 +6,14 @@
 //   * size <= medium cap    -- the same with the medium shape;
 //   * larger                -- per-segment digit histograms (k_seg_hist), then
 //                              one digit-pass launch per digit over the tiles
-//                              of all large segments (k_seg_pass), each
-//                              segment with its own look-back chain.
+//                              of all large segments (k_seg_pass, in
+//                              rs_kernels.h), each segment with its own
+//                              look-back chain.
 // Only device counters decide the work, so the sequence is graph-capturable
 // and needs no host round trip.
 #pragma once
 
+#include "rs.h"
 #include "rs_block.h"
 #include "rs_device.h"
 
@@ -28,7 +30,7 @@ constexpr int kSegSmallClaim = 4;
 constexpr int kSegMediumClaim = 5;
 constexpr int kSegHistClaim = 6;
 constexpr int kSegError = 7;        // bit 0: a segment of 2^30+ elements; bit 1: tiles overflow
-constexpr int kSegPassCounter = 8;  // [8, 16): group counter per pass
+constexpr int kSegPassCounter = 32; // [32, 48): group counter per pass
 constexpr int kSegChunks = 16;      // histogram chunks of the large segments
 constexpr int kSegChunkClaim = 17;
 constexpr int kSegScanClaim = 18;
@@ -97,103 +99,6 @@ __global__ __launch_bounds__(256) void k_seg_classify(SegClassifyArgs a)
             for (uint32_t i = 0; i < nc && cs + i < a.max_chunks; ++i)
                 a.chunk_seg[cs + i] = idx;
         }
-    }
-}
-
-// Digit histograms of the large segments, chunk by chunk: persistent
-// workgroups claim chunks of kSegChunk elements, count all digit positions
-// in LDS and add the counts to the segment's histogram (global atomics).
-struct SegHistArgs {
-    const void *kin;
-    const SegLarge *large;
-    const uint32_t *chunk_seg;
-    uint32_t max_chunks;
-    uint32_t *ctrl;
-    uint32_t *seg_hist;  // [large segment][d][256], zeroed
-    uint32_t *seg_base;  // [large segment][d][256]
-};
-
-template <typename K>
-__global__ __launch_bounds__(256) void k_seg_hist(SegHistArgs a)
-{
-    constexpr int D = KeyTraits<K>::kBits / kRadixBits;
-    constexpr int W = 256 / kWave;
-    __shared__ uint32_t sh[W][D][kRadix];
-    __shared__ uint32_t s_item;
-    const uint32_t t = threadIdx.x;
-    const uint32_t w = t / kWave;
-    const K *keys = (const K *)a.kin;
-    const uint32_t chunks = min(a.ctrl[kSegChunks], a.max_chunks);
-    while (true) {
-        if (t == 0)
-            s_item = atomicAdd(&a.ctrl[kSegChunkClaim], 1u);
-        for (int i = t; i < W * D * kRadix; i += 256)
-            (&sh[0][0][0])[i] = 0;
-        __syncthreads();
-        const uint32_t item = s_item;
-        if (item >= chunks)
-            break;
-        const uint32_t seg = a.chunk_seg[item];
-        const SegLarge rec = a.large[seg];
-        // this chunk's index within its segment: chunks of a segment are
-        // consecutive, so count back to the segment's first chunk
-        uint32_t first = item;
-        while (first > 0 && a.chunk_seg[first - 1] == seg)
-            --first;
-        const uint64_t lo = (uint64_t)(item - first) * kSegChunk;
-        const uint32_t len = rec.size > lo ? (uint32_t)min<uint64_t>(kSegChunk, rec.size - lo) : 0u;
-        const K *sk = keys + rec.start + lo;
-        for (uint32_t i = t; i < len; i += 256) {
-            const K key = sk[i];
-            const uint64_t active = __ballot(1);  // before any branch narrows it
-#pragma unroll
-            for (int p = 0; p < D; ++p) {
-                const uint32_t dg = KeyTraits<K>::digit(key, p * kRadixBits);
-                // a digit held by the whole wave is added once (same-address
-                // LDS atomics serialise)
-                const uint32_t first_dg = __builtin_amdgcn_readfirstlane(dg);
-                if (__ballot(dg != first_dg) == 0) {
-                    if (lane_id() == (uint32_t)__builtin_ctzll(active))
-                        atomicAdd(&sh[w][p][first_dg], (uint32_t)__popcll(active));
-                } else {
-                    atomicAdd(&sh[w][p][dg], 1u);
-                }
-            }
-        }
-        __syncthreads();
-        uint32_t *out = a.seg_hist + (uint64_t)seg * D * kRadix;
-        for (int i = t; i < D * kRadix; i += 256) {
-            uint32_t c = 0;
-#pragma unroll
-            for (int ww = 0; ww < W; ++ww)
-                c += (&sh[ww][0][0])[i];
-            if (c)
-                atomicAdd(&out[i], c);
-        }
-        __syncthreads();
-    }
-}
-
-// seg_base[seg][p] = exclusive scan of seg_hist[seg][p], one workgroup per
-// large segment (persistent).
-template <int D>
-__global__ __launch_bounds__(256) void k_seg_scan(SegHistArgs a)
-{
-    __shared__ uint32_t s_tmp[8];
-    __shared__ uint32_t s_item;
-    const uint32_t t = threadIdx.x;
-    while (true) {
-        if (t == 0)
-            s_item = atomicAdd(&a.ctrl[kSegScanClaim], 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
-        if (item >= a.ctrl[kSegLargeLen])
-            break;
-        for (int p = 0; p < D; ++p) {
-            const uint64_t i = ((uint64_t)item * D + p) * kRadix + t;
-            a.seg_base[i] = block_exclusive_scan_256<256>(a.seg_hist[i], s_tmp);
-        }
-        __syncthreads();
     }
 }
 

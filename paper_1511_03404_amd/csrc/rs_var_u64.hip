@@ -1,0 +1,22 @@
+// Plain-sort kernels of every compiled configuration, u64 keys.
+#include "rs_configs.h"
+#include "rs_ops.h"
+
+namespace rs {
+
+#define RS_KEYS_OPS(R, T, I) SortLaunch<uint64_t, false, R, T, I>::ops(),
+#define RS_PAIRS_OPS(R, T, I) SortLaunch<uint64_t, true, R, T, I>::ops(),
+
+const SortOps *sort_ops_u64(bool has_values, int *count)
+{
+    static const SortOps keys[] = {RS_CONFIGS_U64_KEYS(RS_KEYS_OPS)};
+    static const SortOps pairs[] = {RS_CONFIGS_U64_PAIRS(RS_PAIRS_OPS)};
+    if (has_values) {
+        *count = (int)(sizeof pairs / sizeof pairs[0]);
+        return pairs;
+    }
+    *count = (int)(sizeof keys / sizeof keys[0]);
+    return keys;
+}
+
+}  // namespace rs

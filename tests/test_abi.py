@@ -112,3 +112,78 @@ def test_python_binding_rejects_host_tensors(rs):
         rs.sort_keys(torch.zeros(4, dtype=torch.int32))
     with pytest.raises(TypeError):
         rs.key_bits(torch.zeros(4, dtype=torch.float32))
+
+
+def test_compiled_configurations(rs):
+    """Every kind has its list: the default (index 0) at 8-bit digits, every
+    digit width of 4..8 bits, tiles within one workgroup's limits."""
+    for bits in (32, 64):
+        for pairs in (False, True):
+            cfgs = rs.configs(bits, pairs)
+            assert cfgs[0]["radix_bits"] == 8
+            assert {c["radix_bits"] for c in cfgs} == {4, 5, 6, 7, 8}
+            for c in cfgs:
+                assert 256 <= c["threads"] <= 1024 and c["threads"] % 64 == 0
+                assert c["items"] >= 2 ** c["radix_bits"] // 32  # lane-mask tables fit the staging
+                assert c["threads"] * c["items"] * bits // 8 <= 128 * 1024
+    assert rs.configs(64, True)[0]["threads"] == 512  # registers of 16 u64 pairs per thread
+    L = rs.lib()
+    cnt = ctypes.c_int()
+    assert L.rs_config_count(7, 0, ctypes.byref(cnt)) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_config_count(0, 0, None) == rs.RS_ERR_INVALID_ARGUMENT
+    c = rs.Config()
+    assert L.rs_config_get(0, 0, 99, ctypes.byref(c)) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_config_get(0, 0, -1, ctypes.byref(c)) == rs.RS_ERR_INVALID_ARGUMENT
+
+
+def test_tune_table(rs, ctx):
+    """Per kind, plain/segmented and size class; -1 resets; the workspace
+    size follows the selected configuration."""
+    assert ctx.tune_get(32, True, False, 26) == 0
+    w0 = ctx.workspace_bytes(32, True, 1 << 26)
+    cfgs = rs.configs(32, True)
+    small = min(range(len(cfgs)), key=lambda i: cfgs[i]["threads"] * cfgs[i]["items"])
+    ctx.tune_set(32, True, False, 26, small)
+    assert ctx.tune_get(32, True, False, 26) == small
+    assert ctx.tune_get(32, True, False, 25) == 0
+    assert ctx.tune_get(32, True, True, 26) == 0
+    assert ctx.tune_get(32, False, False, 26) == 0
+    assert ctx.tune_get(64, True, False, 26) == 0
+    # smaller tiles: more look-back words in the workspace
+    assert ctx.workspace_bytes(32, True, 1 << 26) > w0
+    assert ctx.workspace_bytes(32, True, 1 << 25) == ctx.workspace_bytes(32, True, 1 << 25)
+    r4 = [i for i, c in enumerate(cfgs) if c["radix_bits"] == 4][0]
+    ctx.tune_set(32, True, True, -1, r4)
+    for cls in (0, 17, 39):
+        assert ctx.tune_get(32, True, True, cls) == r4
+    ctx.tune_set(32, True, True, -1, -1)
+    assert ctx.tune_get(32, True, True, 17) == 0
+    ctx.tune_set(32, True, False, 26, -1)
+    assert ctx.workspace_bytes(32, True, 1 << 26) == w0
+    L = rs.lib()
+    assert L.rs_tune_set(ctx.handle, 0, 1, 0, 40, 0) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_tune_set(ctx.handle, 0, 1, 0, 5, len(cfgs)) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_tune_set(ctx.handle, 2, 1, 0, 5, 0) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_tune_set(None, 0, 1, 0, 5, 0) == rs.RS_ERR_INVALID_ARGUMENT
+    idx = ctypes.c_int()
+    assert L.rs_tune_get(ctx.handle, 0, 1, 0, -1, ctypes.byref(idx)) == rs.RS_ERR_INVALID_ARGUMENT
+
+
+def test_size_class(rs):
+    assert [rs.size_class(n) for n in (0, 1, 2, 3, 4, 5, 1 << 26, (1 << 26) + 1)] == \
+        [0, 0, 1, 2, 2, 3, 26, 27]
+
+
+def test_tune_cache_round_trip(rs, ctx, tmp_path):
+    """Saved tuning results load into another context; an entry whose
+    configuration no longer matches the library's list is skipped."""
+    from paper_1511_03404_amd import tune
+    cfgs = rs.configs(64, False)
+    good = {"key_bits": 64, "has_values": False, "segmented": True, "size_log2": 30,
+            "n": 1 << 30, "index": 3, "config": cfgs[3], "ms": {}}
+    stale = dict(good, size_log2=29, config=dict(cfgs[3], threads=999))
+    path = tmp_path / "tune.json"
+    tune.save([good, stale], str(path), "test")
+    assert tune.load(str(path), ctx) == 1
+    assert ctx.tune_get(64, False, True, 30) == 3
+    assert ctx.tune_get(64, False, True, 29) == 0
