@@ -1,7 +1,7 @@
 """Serving loop for the radix sort: continuous batching of sort requests.
 
 Requests (n keys of 32 or 64 bits, with or without values) arrive over time.
-The scheduler keeps a FIFO of pending requests and a small number of
+The scheduler keeps pending requests in one FIFO per kind and a small number of
 execution slots (HIP streams).  Whenever a slot is free it forms a batch:
 the oldest pending request fixes the key type, and further pending requests
 of that type join in arrival order while the batch stays under its element
@@ -78,7 +78,11 @@ class Scheduler:
         self.slots = slots
         self.max_batch_elems = max_batch_elems
         self.max_batch_requests = max_batch_requests
-        self.pending: collections.deque = collections.deque()
+        # one FIFO per kind (key width, values); the oldest head overall
+        # fixes the kind of the next batch, so forming a batch costs O(batch),
+        # not O(queue)
+        self.queues: dict[tuple, collections.deque] = {}
+        self._seq = 0
         self.inflight: dict[int, Batch] = {}
         self.mem_used = 0
         self.free_slots = list(range(slots))
@@ -94,30 +98,41 @@ class Scheduler:
             # could never fit: refuse it instead of blocking the queue
             self.rejected.append(req)
             return False
-        self.pending.append(req)
+        self.queues.setdefault(req.kind, collections.deque()).append((self._seq, req))
+        self._seq += 1
         return True
 
+    @property
+    def pending(self) -> list:
+        """Pending requests in arrival order."""
+        return [r for _, r in sorted((e for q in self.queues.values() for e in q),
+                                     key=lambda e: e[0])]
+
+    def _head_queue(self):
+        best = None
+        for q in self.queues.values():
+            if q and (best is None or q[0][0] < best[0][0]):
+                best = q
+        return best
+
     def _form_batch(self):
-        head = self.pending[0]
+        q = self._head_queue()
+        head = q[0][1]
         if self.mem_used + head.footprint() > self.mem_cap:
             return None
+        # requests of a kind are served in arrival order: the first one of
+        # the head's kind that does not fit closes the batch
         chosen, elems, nbytes = [], 0, 0
-        keep = collections.deque()
-        closed = False  # requests of a kind are served in arrival order: the
-        # first one of the head's kind that does not fit closes the batch
-        while self.pending:
-            r = self.pending.popleft()
-            if r.kind == head.kind and not closed:
-                if (len(chosen) < self.max_batch_requests
-                        and (not chosen or elems + r.n <= self.max_batch_elems)
-                        and self.mem_used + nbytes + r.footprint() <= self.mem_cap):
-                    chosen.append(r)
-                    elems += r.n
-                    nbytes += r.footprint()
-                    continue
-                closed = True
-            keep.append(r)
-        self.pending = keep
+        while q:
+            r = q[0][1]
+            if not (len(chosen) < self.max_batch_requests
+                    and (not chosen or elems + r.n <= self.max_batch_elems)
+                    and self.mem_used + nbytes + r.footprint() <= self.mem_cap):
+                break
+            q.popleft()
+            chosen.append(r)
+            elems += r.n
+            nbytes += r.footprint()
         b = Batch(self._next_batch, self.free_slots.pop(), chosen, bytes=nbytes)
         self._next_batch += 1
         return b
@@ -140,7 +155,7 @@ class Scheduler:
                 self.completed.append(r)
             self._release(b)
         launched = 0
-        while self.free_slots and self.pending:
+        while self.free_slots and self._head_queue() is not None:
             b = self._form_batch()
             if b is None:
                 break
@@ -172,7 +187,7 @@ class Scheduler:
         self._release(b)
 
     def idle(self) -> bool:
-        return not self.pending and not self.inflight
+        return self._head_queue() is None and not self.inflight
 
 
 def serve(scheduler: Scheduler, requests: list, clock: Callable[[], float],

@@ -143,3 +143,37 @@ def test_head_of_line_waits_for_memory():
         sch.step(0.0)
     order = [b.requests[0].id for b in be.launched]
     assert order.index(0) < order.index(2)
+
+
+class NullBackend:
+    """Completes every batch at the next step, sorting nothing."""
+
+    def launch(self, batch):
+        return batch
+
+    def done(self, handle):
+        return True
+
+    def finish(self, batch):
+        return {r.id: 0.0 for r in batch.requests}
+
+
+def test_forming_a_batch_does_not_scan_the_whole_queue():
+    """A closed loop queues every request at once; a batch must cost
+    O(batch), not O(queue), or the scheduler dominates at 10^5 requests."""
+    import time
+    qs = datagen.requests(100000, rate_per_s=1e6, lo_log2=10, hi_log2=24, seed=1)
+    reqs = [Request(q["id"], q["n"], q["bits"], q["has_values"], 0.0) for q in qs]
+    sch = Scheduler(NullBackend(), mem_cap=64 << 30, slots=4, max_batch_elems=1 << 25)
+    t0 = time.perf_counter()
+    done = serve(sch, reqs, lambda: 0.0, open_loop=False, sleep=lambda s: None)
+    assert len(done) == 100000
+    assert time.perf_counter() - t0 < 20.0
+    # arrival order within each kind, one kind per batch
+    for kind in {r.kind for r in reqs}:
+        ids = [r.id for r in sorted(done, key=lambda r: (r.batch_id, r.id)) if r.kind == kind]
+        assert ids == sorted(ids)
+    batches = {}
+    for r in done:
+        batches.setdefault(r.batch_id, set()).add(r.kind)
+    assert all(len(k) == 1 for k in batches.values())
