@@ -205,4 +205,23 @@ __device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], int shift, uint
     }
 }
 
+// The same ranks as wave_rank, with the peer mask from R ballots (VALU work)
+// instead of the LDS table: every lane reads its digit's running count, the
+// group's lowest lane advances it.  wc as in wave_rank.
+template <int R, typename K, int ITEMS>
+__device__ __forceinline__ void wave_rank_ballot(const K (&key)[ITEMS], int shift, uint32_t *wc,
+                                                 uint32_t (&rank)[ITEMS])
+{
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t d = digit_of<R>(key[j], shift);
+        const uint64_t m = peer_mask<R>(d);
+        const uint32_t below = lanes_below(m);
+        const uint32_t c = wc[d];
+        rank[j] = c + below;
+        if (below == 0)
+            wc[d] = c + (uint32_t)__popcll(m);
+    }
+}
+
 }  // namespace rs
