@@ -136,7 +136,8 @@ def parse():
     ap.add_argument("--seg-log2", default="4,20",
                     help="segmented workload: log2 of the smallest and largest segment size")
     ap.add_argument("--per-segment-steps", type=int, default=1,
-                    help="segmented workload: timed steps of the one-sort-per-segment form")
+                    help="segmented workload: timed steps of the one-sort-per-segment form "
+                         "(0 skips it)")
     ap.add_argument("--requests", type=int, default=100000,
                     help="serving workload: number of requests per load level")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: streams")
@@ -174,7 +175,12 @@ def bench_serving(args, torch, rs, datagen, dev):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         be.mark_clock_zero(0.0)
-        done = serve(sch, reqs, lambda: time.perf_counter() - t0, open_loop=open_loop)
+        def report(now, submitted, finished):
+            print(f"  t={now:.1f}s submitted {submitted} finished {finished} "
+                  f"in flight {len(sch.inflight)}", file=sys.stderr, flush=True)
+
+        done = serve(sch, reqs, lambda: time.perf_counter() - t0, open_loop=open_loop,
+                     progress=report)
         torch.cuda.synchronize()
         makespan = max(r.done_s for r in done)
         st = summarize(done, makespan)
@@ -184,7 +190,9 @@ def bench_serving(args, torch, rs, datagen, dev):
         return st
 
     # warm-up on a few requests, then the closed loop for R_max
+    print(f"serving {args.requests} requests per load level", file=sys.stderr, flush=True)
     run(requests(1e6)[:64], open_loop=False)
+    print("warm-up done; closed loop", file=sys.stderr, flush=True)
     closed = run(requests(1e6), open_loop=False)
     r_max = closed["requests"] / closed["makespan_s"]
     print(f"closed loop: {closed}", file=sys.stderr, flush=True)
@@ -219,8 +227,10 @@ def bench_segmented(args, torch, rs, datagen, dev):
     lo, hi = (int(x) for x in args.seg_log2.split(","))
     S = args.segments
     t0 = time.perf_counter()
+    print(f"generating {S} segments on the host", file=sys.stderr, flush=True)
     keys, vals, off = datagen.segmented(num_segments=S, lo_log2=lo, hi_log2=hi, bits=32, seed=1)
     gen_s = time.perf_counter() - t0
+    print(f"generated {off[-1]} elements in {gen_s:.1f} s", file=sys.stderr, flush=True)
     total = int(off[-1])
     sizes = np.diff(off.astype(np.int64))
     kd = torch.from_numpy(keys).to(dev)
@@ -248,6 +258,7 @@ def bench_segmented(args, torch, rs, datagen, dev):
     for _ in range(args.warmup):
         batched()
     torch.cuda.synchronize()
+    print("timing the batched form", file=sys.stderr, flush=True)
     ctx.profile_reset()
     ctx.profile_enable(True)
     ev0.record()
@@ -263,6 +274,7 @@ def bench_segmented(args, torch, rs, datagen, dev):
         kern.setdefault(name, []).append(ms)
     kern_ms = {k: round(sum(v) / args.steps, 4) for k, v in kern.items()}
 
+    print(f"batched: {batched_ms:.3f} ms; graph capture and replay", file=sys.stderr, flush=True)
     # the same enqueue captured once into a graph and replayed
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
@@ -289,13 +301,15 @@ def bench_segmented(args, torch, rs, datagen, dev):
                 ko[a:b].copy_(kd[a:b])
                 vo[a:b].copy_(vd[a:b])
 
-    per_segment()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.per_segment_steps):
+    per_seg_ms = None
+    if args.per_segment_steps > 0:
         per_segment()
-    torch.cuda.synchronize()
-    per_seg_ms = (time.perf_counter() - t0) * 1e3 / args.per_segment_steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.per_segment_steps):
+            per_segment()
+        torch.cuda.synchronize()
+        per_seg_ms = (time.perf_counter() - t0) * 1e3 / args.per_segment_steps
 
     large = sizes[sizes > 16384]
     pass_ms = kern.get("k_seg_pass_u32", [])
@@ -329,9 +343,9 @@ def bench_segmented(args, torch, rs, datagen, dev):
         "batched_ms": round(batched_ms, 3),
         "graph_replay_ms": round(graph_ms, 3),
         "graph_replay_Mkeys_s": round(total / graph_ms / 1e3, 1),
-        "per_segment_launch_ms": round(per_seg_ms, 3),
-        "per_segment_launch_Mkeys_s": round(total / per_seg_ms / 1e3, 1),
-        "speedup_batched_vs_per_segment": round(per_seg_ms / batched_ms, 2),
+        "per_segment_launch_ms": round(per_seg_ms, 3) if per_seg_ms else None,
+        "per_segment_launch_Mkeys_s": round(total / per_seg_ms / 1e3, 1) if per_seg_ms else None,
+        "speedup_batched_vs_per_segment": round(per_seg_ms / batched_ms, 2) if per_seg_ms else None,
         "hbm_frac_whole_batch": round(4 * 2 * total * 8 / (batched_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "kernels_ms": kern_ms,
         "roofline": roofline,

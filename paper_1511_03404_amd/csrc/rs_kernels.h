@@ -308,11 +308,16 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 //     from the global counter and publishes the group's id in the XCD's
 //     list; the other claims of the same group wait for that id (the opener
 //     is running, so the wait is short).
-// Groups are opened in global order and the tiles of one XCD's groups
-// increase with its claim counter, so the lowest unfinished tile is always
-// held or next to be claimed by a running workgroup of its XCD (workgroups
-// keep claiming until the groups run out): the look-back waits cannot
-// depend on a workgroup that has not started.
+// An XCD's opener takes its global id only after the XCD's previous group is
+// open, so the tiles of one XCD's groups increase with its claim counter
+// (two openers racing between their two atomics could otherwise give the
+// later group the lower tiles).  Then a workgroup's claims are increasing
+// tiles, an empty claim means no later claim of the XCD gets a tile, and the
+// lowest unfinished tile is always held or next to be claimed by a running
+// workgroup of its XCD (workgroups keep claiming until the groups run out):
+// the look-back waits cannot depend on a workgroup that has not started,
+// and claiming ahead cannot leave a higher tile waiting on a lower one that
+// nobody will claim.
 //
 // claims layout: [0, 8) per-XCD claim counters, then [8 + x*G + j] the id+1
 // of group j of XCD x (0 = not yet published, kNoTile = no group left).
@@ -333,8 +338,18 @@ __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
                 return kNoTile;
             uint32_t v;
             if (i == 0) {
-                const uint32_t g = atomicAdd(ctr, 1u);
-                v = g < a.num_groups ? g + 1 : kNoTile;
+                uint32_t prev = 1;
+                if (j > 0) {
+                    while ((prev = __hip_atomic_load(&list[j - 1], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                        __builtin_amdgcn_s_sleep(1);
+                }
+                if (prev == kNoTile) {
+                    v = kNoTile;
+                } else {
+                    const uint32_t g = atomicAdd(ctr, 1u);
+                    v = g < a.num_groups ? g + 1 : kNoTile;
+                }
                 __hip_atomic_store(&list[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 while ((v = __hip_atomic_load(&list[j], __ATOMIC_RELAXED,

@@ -191,16 +191,24 @@ class Scheduler:
 
 
 def serve(scheduler: Scheduler, requests: list, clock: Callable[[], float],
-          open_loop: bool = True, sleep: Callable[[float], None] = time.sleep):
+          open_loop: bool = True, sleep: Callable[[float], None] = time.sleep,
+          progress: Optional[Callable[[float, int, int], None]] = None,
+          progress_every_s: float = 5.0):
     """Feed requests at their arrival times (open loop) or all at once
-    (closed loop, arrival = 0) and run the scheduler until all complete."""
+    (closed loop, arrival = 0) and run the scheduler until all complete.
+    progress(now, submitted, finished) is called about every
+    progress_every_s seconds of the serving clock."""
     reqs = sorted(requests, key=lambda r: r.arrival_s)
     if not open_loop:
         for r in reqs:
             r.arrival_s = 0.0
     i = 0
+    next_report = progress_every_s
     while i < len(reqs) or not scheduler.idle():
         now = clock()
+        if progress is not None and now >= next_report:
+            progress(now, i, len(scheduler.completed) + len(scheduler.failed))
+            next_report = now + progress_every_s
         while i < len(reqs) and reqs[i].arrival_s <= now:
             scheduler.submit(reqs[i], now)
             i += 1

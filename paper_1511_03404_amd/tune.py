@@ -66,8 +66,15 @@ def _candidates(key_bits, has_values, candidates):
     return cfgs, idx
 
 
+# a configuration replaces the default only if it is faster by this fraction:
+# ties would otherwise flip the choice from one run to the next
+MARGIN = 0.03
+
+
 def _result(key_bits, has_values, segmented, n, cls, cfgs, times, note=None):
     best = min(times, key=times.get)
+    if 0 in times and times[0] <= times[best] * (1.0 + MARGIN):
+        best = 0
     r = {"key_bits": key_bits, "has_values": bool(has_values), "segmented": bool(segmented),
          "size_log2": cls, "n": int(n), "index": best, "config": cfgs[best],
          "ms": {str(i): round(t, 5) for i, t in sorted(times.items())}}
