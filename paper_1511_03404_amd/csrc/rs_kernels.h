@@ -315,9 +315,7 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 // tiles, an empty claim means no later claim of the XCD gets a tile, and the
 // lowest unfinished tile is always held or next to be claimed by a running
 // workgroup of its XCD (workgroups keep claiming until the groups run out):
-// the look-back waits cannot depend on a workgroup that has not started,
-// and claiming ahead cannot leave a higher tile waiting on a lower one that
-// nobody will claim.
+// the look-back waits cannot depend on a workgroup that has not started.
 //
 // claims layout: [0, 8) per-XCD claim counters, then [8 + x*G + j] the id+1
 // of group j of XCD x (0 = not yet published, kNoTile = no group left).
@@ -423,21 +421,8 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
     }
 }
 
-// Where one tile's elements are and where its digit runs go.
-struct TileRef {
-    uint64_t src_off;  // first element of the tile in the source arrays
-    uint64_t dst_off;  // first element of the sequence its digit runs land in
-    uint32_t valid;    // elements in the tile
-    uint32_t limit;    // length of that sequence (destination indices are below it)
-    uint32_t first;    // first tile of its look-back chain
-    uint32_t seg;      // segment of a segmented sort (for its digit offsets)
-};
-
-// LDS of one digit pass.  Keys and values have staging buffers of their own;
-// the per-wave lane-mask tables of the ranking live in the key buffer, which
-// is free until the keys are staged.  Tiles are claimed two iterations ahead
-// into two slots (iteration i's tile sits in slot i % 2).
-template <typename K, typename C, bool HAS_V>
+// LDS of one digit pass.
+template <typename K, typename C>
 struct PassLds {
     static constexpr int W = C::kThreads / kWave;
     static constexpr size_t kStageBytes = (size_t)C::kTile * sizeof(K);
@@ -446,10 +431,8 @@ struct PassLds {
     uint32_t wcnt[W * C::kBins];  // per wave and digit: count, then base in tile
     uint32_t gbase[C::kBins];
     uint32_t tmp[8];
-    uint32_t slot_tile[2];
-    TileRef slot_ref[2];
+    uint32_t tile;
     __attribute__((aligned(16))) unsigned char stage[kStageBytes];
-    __attribute__((aligned(16))) unsigned char vstage[HAS_V ? kStageBytes : 16];
 
     // zero the counters and the lane-mask tables before a tile
     __device__ __forceinline__ void clear(uint32_t t)
@@ -461,39 +444,17 @@ struct PassLds {
     }
 };
 
-// The thread that claims tiles during the look-back: one of a wave with no
-// digit bin (such waves are idle then), else thread 0.
-template <typename C>
-constexpr uint32_t claim_thread()
-{
-    return C::kThreads - kWave >= C::kBins ? C::kThreads - kWave : 0;
-}
-
-__device__ __forceinline__ uint32_t uniform(uint32_t v)
-{
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v)
-{
-    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
-}
-
-// One digit pass over claimed tiles (the paper's counting sort, Section 2.6,
-// spread over workgroups).  Per tile: rank every element among its wave's
-// elements of the same digit, publish the tile's digit counts, stage keys
-// and values in LDS in digit order (tile-local offsets), then -- while the
-// next tile's loads are in flight -- the decoupled look-back over the
-// earlier tiles of the chain gives the tile's global offsets, and each digit
-// run is written with consecutive lanes on consecutive addresses.
-//
-// Res maps a tile to its TileRef (resolve) and gives a digit's starting
-// offset (dbase); the claim thread resolves a tile when it claims it, two
-// iterations before its use, so no iteration waits on that lookup.
-template <typename K, typename V, bool HAS_V, typename C, typename Res>
-__device__ __forceinline__ void run_pass(PassLds<K, C, HAS_V> &L, const PassArgs &claim,
-                                         const Res &res, const K *sk, const V *sv, K *dk, V *dv,
-                                         uint32_t *status, int shift, bool ballot_rank)
+// One tile of a digit pass (the paper's counting sort, Section 2.6, spread
+// over workgroups): rank, publish the tile's digit counts, decoupled
+// look-back over tiles [first_tile, tile), stage in LDS, write the digit
+// runs.  The tile's elements are tk/tv[0, valid); destination index i of the
+// digit-sorted sequence is dk/dv[i] for i < limit.  dbase (threads < 2^R) is
+// the digit's starting offset in that sequence.  Ends with a barrier.
+template <typename K, typename V, bool HAS_V, typename C>
+__device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V *tv, K *dk,
+                                          V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
+                                          uint32_t first_tile, uint32_t *status, uint32_t dbase,
+                                          int shift, bool ballot_rank)
 {
     constexpr int R = C::kRadixBits;
     constexpr uint32_t NB = C::kBins;
@@ -504,7 +465,7 @@ __device__ __forceinline__ void run_pass(PassLds<K, C, HAS_V> &L, const PassArgs
     constexpr int LBW = C::kLookback;
     static_assert(sizeof(V) == sizeof(K), "values have the key's width");
     K *s_k = (K *)L.stage;
-    V *s_v = (V *)L.vstage;
+    V *s_v = (V *)L.stage;
     uint64_t *s_mask = (uint64_t *)L.stage;
     const uint32_t t = threadIdx.x;
     const uint32_t w = t / kWave;
@@ -512,182 +473,115 @@ __device__ __forceinline__ void run_pass(PassLds<K, C, HAS_V> &L, const PassArgs
     const uint32_t off0 = w * (kWave * ITEMS) + lane;
     uint32_t *wc = L.wcnt + w * NB;
 
-    // the first two tiles
-    if (t == 0) {
-        const uint32_t x = xcc_id();
-#pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            const uint32_t tl = claim_tile<C::kGroup>(claim, x);
-            L.slot_tile[sl] = tl;
-            if (tl != kNoTile)
-                L.slot_ref[sl] = res.resolve(tl);
-        }
-    }
-    L.clear(t);
-    __syncthreads();
-    uint32_t tile = uniform(L.slot_tile[0]);
-    if (tile == kNoTile)
-        return;
-    TileRef cur = L.slot_ref[0];
+    // load: item j of lane l is element j*64 + l of this wave's run
     K key[ITEMS];
     V val[HAS_V ? ITEMS : 1];
-    load_tile<K, V, HAS_V, ITEMS>(sk + uniform64(cur.src_off), HAS_V ? sv + uniform64(cur.src_off) : nullptr,
-                                  uniform(cur.valid), off0, key, val, uniform(cur.valid) == (uint32_t)T);
-    uint32_t dbase = t < NB ? res.dbase(cur, t) : 0u;
+    load_tile<K, V, HAS_V, ITEMS>(tk, tv, valid, off0, key, val, valid == (uint32_t)T);
 
-    for (uint32_t it = 0;; ++it) {
-        // count: stable rank of every item among the wave's items of its digit
-        uint32_t rank[ITEMS];
-        if (ballot_rank || w < (uint32_t)C::kBallotWaves)
-            wave_rank_ballot<R, K, ITEMS>(key, shift, wc, rank);
-        else
-            wave_rank<R, K, ITEMS>(key, shift, wc, s_mask + w * NB, lane, rank);
-        __syncthreads();
+    // count: stable rank of every item among the wave's items of its digit
+    uint32_t rank[ITEMS];
+    if (ballot_rank || w < (uint32_t)C::kBallotWaves)
+        wave_rank_ballot<R, K, ITEMS>(key, shift, wc, rank);
+    else
+        wave_rank<R, K, ITEMS>(key, shift, wc, s_mask + w * NB, lane, rank);
+    __syncthreads();
 
-        // scan: wave offsets per digit, tile count, publish the aggregate,
-        // tile-local offsets
-        const uint32_t first = uniform(cur.first);
-        uint32_t cnt = 0;
-        if (t < NB) {
+    // scan: wave offsets per digit, tile count, publish the aggregate,
+    // tile-local offsets
+    uint32_t cnt = 0;
+    if (t < NB) {
 #pragma unroll
-            for (int ww = 0; ww < W; ++ww) {
-                const uint32_t c = L.wcnt[ww * NB + t];
-                L.wcnt[ww * NB + t] = cnt;
-                cnt += c;
-            }
-            __hip_atomic_store(&status[(uint64_t)tile * NB + t],
-                               (tile == first ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        for (int ww = 0; ww < W; ++ww) {
+            const uint32_t c = L.wcnt[ww * NB + t];
+            L.wcnt[ww * NB + t] = cnt;
+            cnt += c;
         }
-        const uint32_t excl = bins_exclusive_scan<NB>(cnt, L.tmp);
-        if (t < NB) {
+        __hip_atomic_store(&status[(uint64_t)tile * NB + t],
+                           (tile == first_tile ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t excl = bins_exclusive_scan<NB>(cnt, L.tmp);
+    if (t < NB) {
+        // decoupled look-back: read LBW predecessors per round trip, add
+        // their counts in order up to the first inclusive one; on a tile
+        // that has not published yet, wait and re-read from there
+        uint32_t prefix = 0;
+        int64_t k = (int64_t)tile - 1;
+        const int64_t lo = first_tile;
+        while (k >= lo) {
+            uint32_t st[LBW];
 #pragma unroll
-            for (int ww = 0; ww < W; ++ww)
-                L.wcnt[ww * NB + t] += excl;
-        }
-        __syncthreads();
-
-        // stage keys and values in digit order (the tile-local offsets do
-        // not wait for the look-back)
+            for (int i = 0; i < LBW; ++i)
+                st[i] = (k - i >= lo)
+                            ? __hip_atomic_load(&status[(uint64_t)(k - i) * NB + t],
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : kFlagInc;
+            int used = 0;
+            bool done = false;
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const uint32_t pos = rank[j] + wc[digit_of<R>(key[j], shift)];
-            s_k[pos] = key[j];
-            if constexpr (HAS_V)
-                s_v[pos] = val[j];
-        }
-
-        // the next tile (claimed two iterations ago): its loads fly during
-        // the look-back and the writes of this tile
-        const uint32_t ns = (it + 1) & 1;
-        const uint32_t next = uniform(L.slot_tile[ns]);
-        TileRef nref{};
-        uint32_t ndbase = 0;
-        if (next != kNoTile) {
-            nref = L.slot_ref[ns];
-            const uint64_t so = uniform64(nref.src_off);
-            const uint32_t nv = uniform(nref.valid);
-            load_tile<K, V, HAS_V, ITEMS>(sk + so, HAS_V ? sv + so : nullptr, nv, off0, key, val,
-                                          nv == (uint32_t)T);
-            ndbase = t < NB ? res.dbase(nref, t) : 0u;
-        }
-        // the tile after it, into the slot this iteration's tile came from
-        if (t == claim_thread<C>()) {
-            const uint32_t tl = claim_tile<C::kGroup>(claim, xcc_id());
-            L.slot_tile[it & 1] = tl;
-            if (tl != kNoTile)
-                L.slot_ref[it & 1] = res.resolve(tl);
-        }
-
-        if (t < NB) {
-            // decoupled look-back: read LBW predecessors per round trip, add
-            // their counts in order up to the first inclusive one; on a tile
-            // that has not published yet, wait and re-read from there
-            uint32_t prefix = 0;
-            int64_t k = (int64_t)tile - 1;
-            const int64_t lo = first;
-            while (k >= lo) {
-                uint32_t st[LBW];
-#pragma unroll
-                for (int i = 0; i < LBW; ++i)
-                    st[i] = (k - i >= lo)
-                                ? __hip_atomic_load(&status[(uint64_t)(k - i) * NB + t],
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                : kFlagInc;
-                int used = 0;
-                bool done = false;
-#pragma unroll
-                for (int i = 0; i < LBW; ++i) {
-                    if (!done && used == i) {
-                        const uint32_t f = st[i] & kFlagMask;
-                        if (f != 0) {
-                            prefix += st[i] & kCountMask;
-                            done = f == kFlagInc;
-                            used = i + 1;
-                        }
+            for (int i = 0; i < LBW; ++i) {
+                if (!done && used == i) {
+                    const uint32_t f = st[i] & kFlagMask;
+                    if (f != 0) {
+                        prefix += st[i] & kCountMask;
+                        done = f == kFlagInc;
+                        used = i + 1;
                     }
                 }
-                if (done)
-                    break;
-                k -= used;
-                if (used < LBW)
-                    __builtin_amdgcn_s_sleep(1);
             }
-            if (tile != first)
-                __hip_atomic_store(&status[(uint64_t)tile * NB + t], kFlagInc | (prefix + cnt),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            L.gbase[t] = dbase + prefix - excl;
+            if (done)
+                break;
+            k -= used;
+            if (used < LBW)
+                __builtin_amdgcn_s_sleep(1);
         }
-        __syncthreads();
-
-        // place: each digit run with consecutive lanes on consecutive addresses
-        {
-            const uint64_t doff = uniform64(cur.dst_off);
-            const uint32_t limit = uniform(cur.limit);
-            K *dkt = dk + doff;
-            V *dvt = HAS_V ? dv + doff : nullptr;
+        if (tile != first_tile)
+            __hip_atomic_store(&status[(uint64_t)tile * NB + t], kFlagInc | (prefix + cnt),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        L.gbase[t] = dbase + prefix - excl;
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t pos = i * THREADS + t;
-                const K k = s_k[pos];
-                const uint32_t dst = L.gbase[digit_of<R>(k, shift)] + pos;
-                if (dst < limit) {
-                    store_at(dkt, dst, k);
-                    if constexpr (HAS_V)
-                        store_at(dvt, dst, s_v[pos]);
-                }
-            }
-        }
-        __syncthreads();  // the staging buffers are reused by the next tile
-        if (next == kNoTile)
-            break;
-        L.clear(t);
-        __syncthreads();
-        tile = next;
-        cur = nref;
-        dbase = ndbase;
+        for (int ww = 0; ww < W; ++ww)
+            L.wcnt[ww * NB + t] += excl;
     }
-}
+    __syncthreads();
 
-// Tiles of a plain sort: tile i holds elements [i*T, min((i+1)*T, n)).
-struct PlainTiles {
-    uint32_t n;
-    uint32_t tile_elems;
-    const uint32_t *digit_base;  // row of this pass
-    __device__ TileRef resolve(uint32_t tile) const
-    {
-        const uint64_t lo = (uint64_t)tile * tile_elems;
-        return TileRef{lo, 0, (uint32_t)std::min<uint64_t>(tile_elems, n - lo), n, 0, 0};
+    // place: stage the keys in rank order, then write each digit run out
+    // with consecutive lanes on consecutive addresses; then the values
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        rank[j] += wc[digit_of<R>(key[j], shift)];  // position in the tile
+        s_k[rank[j]] = key[j];
     }
-    __device__ uint32_t dbase(const TileRef &, uint32_t t) const { return digit_base[t]; }
-};
+    __syncthreads();
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t pos = i * THREADS + t;
+        const K k = s_k[pos];
+        dst[i] = L.gbase[digit_of<R>(k, shift)] + pos;
+        if (dst[i] < limit)
+            store_at(dk, dst[i], k);
+    }
+    if constexpr (HAS_V) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            s_v[rank[j]] = val[j];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (dst[i] < limit)
+                store_at(dv, dst[i], s_v[i * THREADS + t]);
+    }
+    __syncthreads();  // LDS is reused by the next tile
+}
 
 template <typename K, typename V, bool HAS_V, typename C>
 __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
 {
     constexpr int THREADS = C::kThreads;
     constexpr int T = C::kTile;
-    __shared__ PassLds<K, C, HAS_V> L;
+    __shared__ PassLds<K, C> L;
 
     const uint32_t t = threadIdx.x;
     const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
@@ -708,11 +602,26 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
     }
     const uint32_t src = (plan >> kPlanSrcShift) & 3u;
     const uint32_t dstb = (plan >> kPlanDstShift) & 3u;
-    const PlainTiles res{a.n, (uint32_t)T, a.digit_base};
-    run_pass<K, V, HAS_V, C>(L, a, res, pick<const K>(a.b, src, false),
-                             HAS_V ? pick<const V>(a.b, src, true) : nullptr,
-                             pick<K>(a.b, dstb, false), HAS_V ? pick<V>(a.b, dstb, true) : nullptr,
-                             a.status, a.shift, (plan & kPlanBallot) != 0);
+    const K *sk = pick<const K>(a.b, src, false);
+    const V *sv = HAS_V ? pick<const V>(a.b, src, true) : nullptr;
+    K *dk = pick<K>(a.b, dstb, false);
+    V *dv = HAS_V ? pick<V>(a.b, dstb, true) : nullptr;
+    // this digit's starting offset, fetched early (used after the look-back)
+    const uint32_t dbase = t < (uint32_t)C::kBins ? a.digit_base[t] : 0u;
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    while (true) {
+        if (t == 0)
+            L.tile = claim_tile<C::kGroup>(a, xcc);
+        L.clear(t);
+        __syncthreads();
+        const uint32_t tile = L.tile;
+        if (tile == kNoTile)
+            break;
+        const uint64_t tb = (uint64_t)tile * T;
+        const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tb);
+        pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile,
+                                  0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -842,44 +751,41 @@ struct SegPassArgs {
     int d;
 };
 
-// Tiles of the large segments: tile i is tile i - tile_start of its segment.
-struct SegTiles {
-    const SegLarge *large;
-    const uint32_t *tile_seg;
-    const uint32_t *seg_base;  // [large segment][d][2^R]
-    uint32_t tile_elems;
-    uint32_t pass;
-    uint32_t d;
-    uint32_t bins;
-    __device__ TileRef resolve(uint32_t tile) const
-    {
-        const uint32_t seg = tile_seg[tile];
-        const SegLarge rec = large[seg];
-        const uint32_t lt = tile - rec.tile_start;
-        const uint32_t lo = lt * tile_elems;
-        const uint32_t valid = rec.size > lo ? std::min<uint32_t>(tile_elems, rec.size - lo) : 0u;
-        return TileRef{rec.start + lo, rec.start, valid, rec.size, rec.tile_start, seg};
-    }
-    __device__ uint32_t dbase(const TileRef &r, uint32_t t) const
-    {
-        return seg_base[((uint64_t)r.seg * d + pass) * bins + t];
-    }
-};
-
 template <typename K, typename V, bool HAS_V, typename C>
 __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
 {
-    __shared__ PassLds<K, C, HAS_V> L;
+    constexpr int T = C::kTile;
+    constexpr uint32_t NB = C::kBins;
+    __shared__ PassLds<K, C> L;
+    const uint32_t t = threadIdx.x;
     PassArgs pa{};
     pa.ctrl = a.ctrl + (kSegPassCounter - kCtrlTileCounter);
     pa.pass = a.pass;
     pa.claims = a.claims;
     pa.num_tiles = std::min(a.ctrl[kSegTiles], a.max_tiles);
     pa.num_groups = (pa.num_tiles + C::kGroup - 1) / C::kGroup;
-    const SegTiles res{a.large,        a.tile_seg,         a.seg_base,      (uint32_t)C::kTile,
-                       (uint32_t)a.pass, (uint32_t)a.d, (uint32_t)C::kBins};
-    run_pass<K, V, HAS_V, C>(L, pa, res, (const K *)a.src_k, (const V *)a.src_v, (K *)a.dst_k,
-                             (V *)a.dst_v, a.status, a.shift, false);
+    const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    while (true) {
+        if (t == 0)
+            L.tile = claim_tile<C::kGroup>(pa, xcc);
+        L.clear(t);
+        __syncthreads();
+        const uint32_t tile = L.tile;
+        if (tile == kNoTile)
+            break;
+        const uint32_t seg = a.tile_seg[tile];
+        const SegLarge rec = a.large[seg];
+        const uint32_t lt = tile - rec.tile_start;
+        const uint32_t first = lt * T;
+        const uint32_t valid = rec.size > first ? std::min<uint32_t>(T, rec.size - first) : 0u;
+        const uint32_t dbase = t < NB ? a.seg_base[((uint64_t)seg * a.d + a.pass) * NB + t] : 0u;
+        const uint64_t off = rec.start + (uint64_t)lt * T;
+        pass_tile<K, V, HAS_V, C>(L, (const K *)a.src_k + off,
+                                  HAS_V ? (const V *)a.src_v + off : nullptr,
+                                  (K *)a.dst_k + rec.start,
+                                  HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
+                                  tile, rec.tile_start, a.status, dbase, a.shift, false);
+    }
 }
 
 // In-place segmented sort with an odd number of passes: the large segments
