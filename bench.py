@@ -128,7 +128,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner: use the default configuration (index 0)")
-    ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--cpu-sample-log2", type=int, default=26,
+                    help="cpu_baseline: log2 of the elements the oracle sorts per distribution")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="print the traffic summary of rocprofv3 --pmc runs under DIR and exit")
     ap.add_argument("--segments", type=int, default=20000,
@@ -355,7 +356,7 @@ def bench_segmented(args, torch, rs, datagen, dev):
     }
     if not args.no_cpu_baseline:
         import oracle
-        m = min(S, 200)
+        m = min(S, 4000)  # about a fifth of the batch: ~10 s of one core
         a, b = 0, int(off[m])
         t0 = time.perf_counter()
         oracle.segmented_sort(keys[a:b], vals[a:b], off[:m + 1])
@@ -540,7 +541,8 @@ def main():
         "per_distribution": per,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(bits, has_v, dists, args.cpu_sample_log2)
+        out["cpu_baseline"] = cpu_baseline(bits, has_v, dists,
+                                           min(args.cpu_sample_log2, n.bit_length() - 1))
     print(json.dumps(out), flush=True)
 
 
