@@ -122,7 +122,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="u32_pairs",
-                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented", "serving"])
+                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented", "serving", "grid"])
     ap.add_argument("--dists", default="all",
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,6 +142,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=100000,
                     help="serving workload: number of requests per load level")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: streams")
+    ap.add_argument("--grid-max-log2", type=int, default=25,
+                    help="grid workload: largest log2 size (64-bit kinds stop one lower)")
+    ap.add_argument("--grid-oracle-max-log2", type=int, default=22,
+                    help="grid workload: time the oracle up to this log2 size (speedup column)")
     return ap.parse_args()
 
 
@@ -217,6 +221,77 @@ def bench_serving(args, torch, rs, datagen, dev):
         "r_max_req_s": round(r_max, 1),
         "closed_loop": closed,
         "open_loop": levels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_grid(args, torch, rs, datagen, dev):
+    """The paper's measurement grid (Section 3): every kind (32/64-bit keys,
+    with and without values) x the six distributions x n = 2^15 .. 2^25
+    (2^24 for 64-bit keys) and the 2^k + 2^(k-1) lengths between them.
+    Each point is the mean time of `steps` sorts after `warmup`, inputs
+    resident in HBM, out-of-place; the oracle's rate on the same input gives
+    the speedup up to --grid-oracle-max-log2."""
+    import oracle
+    sizes = []
+    for k in range(15, args.grid_max_log2 + 1):
+        sizes.append(1 << k)
+        if k < args.grid_max_log2:
+            sizes.append((1 << k) + (1 << (k - 1)))
+    ctx = rs.context(0)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    points = []
+    for bits, has_v in ((32, False), (32, True), (64, False), (64, True)):
+        kind = f"u{bits}_{'pairs' if has_v else 'keys'}"
+        limit = args.grid_max_log2 - (1 if bits == 64 else 0)
+        for n in sizes:
+            if n > (1 << limit):
+                continue
+            ws = torch.empty(ctx.workspace_bytes(bits, has_v, n), dtype=torch.uint8, device=dev)
+            for d in datagen.DISTRIBUTIONS:
+                kh = datagen.keys(d, n, bits, seed=1)
+                vh = datagen.values(n, bits) if has_v else None
+                k = torch.from_numpy(kh).to(dev)
+                v = torch.from_numpy(vh).to(dev) if has_v else None
+                ko = torch.empty_like(k)
+                vo = torch.empty_like(k) if has_v else None
+
+                def go():
+                    if has_v:
+                        rs.sort_pairs(k, v, ko, vo, ctx=ctx, workspace=ws)
+                    else:
+                        rs.sort_keys(k, ko, ctx=ctx, workspace=ws)
+                for _ in range(args.warmup):
+                    go()
+                ev0.record()
+                for _ in range(args.steps):
+                    go()
+                ev1.record()
+                ev1.synchronize()
+                ms = ev0.elapsed_time(ev1) / args.steps
+                pt = {"kind": kind, "dist": d, "n": n, "ms": round(ms, 5),
+                      "Mkeys_s": round(n / ms / 1e3, 1)}
+                if n <= (1 << args.grid_oracle_max_log2):
+                    t0 = time.perf_counter()
+                    oracle.sort(kh, vh)
+                    cpu = time.perf_counter() - t0
+                    pt["oracle_Mkeys_s"] = round(n / cpu / 1e6, 2)
+                    pt["speedup"] = round(cpu * 1e3 / ms, 1)
+                points.append(pt)
+            print(f"{kind} n={n} done", file=sys.stderr, flush=True)
+    big = [p for p in points if p["kind"] == "u32_pairs" and p["n"] == (1 << args.grid_max_log2)]
+    out = {
+        "metric": "Mkeys/s over the paper's grid of kinds, distributions and sizes",
+        "value": round(sum(p["Mkeys_s"] for p in big) / max(1, len(big)), 1),
+        "unit": "Mkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32+u64", "data": "synthetic",
+        "config": {"workload": "grid: u32/u64 keys and pairs x 6 distributions x n = 2^15.."
+                               f"2^{args.grid_max_log2} and 2^k+2^(k-1); value = mean over the six "
+                               f"distributions of u32 pairs at 2^{args.grid_max_log2}",
+                   "sizes": sizes},
+        "oracle_cores": 1,
+        "points": points,
     }
     print(json.dumps(out), flush=True)
 
@@ -428,6 +503,9 @@ def main():
         return
     if args.workload == "serving":
         bench_serving(args, torch, rs, datagen, dev)
+        return
+    if args.workload == "grid":
+        bench_grid(args, torch, rs, datagen, dev)
         return
     n, bits, has_v, wdesc = WORKLOADS[args.workload]
     dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")

@@ -29,6 +29,9 @@ namespace rs {
 // Consecutive tiles claimed as a group (see claim_tile).
 constexpr int kClaimGroup = 8;
 
+// Per-XCD claim counters (XCC_ID has 3 bits; gfx950 has 8 XCDs).
+constexpr uint32_t kXcdSlots = 8;
+
 // One wave in kBallotShare ranks with ballots (see PassCfg::kBallotWaves).
 constexpr int kBallotShare = 4;
 
@@ -290,7 +293,7 @@ struct PassArgs {
 // Which compute die (XCD) this wave runs on, from the XCC_ID hardware register.
 __device__ __forceinline__ uint32_t xcc_id()
 {
-    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & 7u;
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & (kXcdSlots - 1);
 }
 
 constexpr uint32_t kNoTile = 0xFFFFFFFFu;
@@ -328,7 +331,7 @@ __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
         const uint32_t t = atomicAdd(ctr, 1u);
         return t < a.num_tiles ? t : kNoTile;
     } else {
-        uint32_t *list = a.claims + 8 + (uint64_t)xcc * a.num_groups;
+        uint32_t *list = a.claims + kXcdSlots + (uint64_t)xcc * a.num_groups;
         while (true) {
             const uint32_t k = atomicAdd(&a.claims[xcc], 1u);
             const uint32_t j = k / GROUP, i = k % GROUP;

@@ -215,7 +215,7 @@ static Layout make_layout(int key_bytes, bool has_values, uint64_t n, const Sort
     L.off_base = o;
     o = align_up(o + (uint64_t)L.d * L.bins * 4, 256);
     L.off_status = o;
-    L.claim_words = 8 + 8 * L.tiles;  // per-XCD counters + per-XCD group lists
+    L.claim_words = kXcdSlots * (1 + L.tiles);  // per-XCD counters + per-XCD group lists
     L.status_bytes = align_up((uint64_t)L.d * (L.tiles * L.bins + L.claim_words) * 4, 16);
     o = align_up(o + L.status_bytes, 256);
     L.off_tmp_k = o;
@@ -428,9 +428,13 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     launch(ctx, s, "k_plan", [&] { op.plan(pl, s); });
 
     // workgroups loop over claimed tiles: launch only what fits on the device
-    // at once (more would start at the end just to find no work)
+    // at once (more would start at the end just to find no work).  Tiles are
+    // claimed in groups per XCD and workgroups are dealt to the XCDs in turn,
+    // so a small sort launches up to one workgroup per tile on every XCD:
+    // otherwise an XCD holding a group could have fewer workgroups than tiles
+    // and process them one after another.
     const uint32_t pass_grid = (uint32_t)std::min<uint64_t>(
-        L.tiles, (uint64_t)resident_blocks(op.pass_kernel, op.threads) * ctx_cus(ctx));
+        L.tiles * kXcdSlots, (uint64_t)resident_blocks(op.pass_kernel, op.threads) * ctx_cus(ctx));
     for (int p = 0; p < L.d; ++p) {
         PassArgs pa{};
         pa.b = b;
@@ -483,7 +487,7 @@ static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total,
     const uint64_t T = (uint64_t)op.tile;
     // every large segment adds at most one partial tile
     L.max_tiles = total / T + nseg + 1;
-    L.claim_words = 8 + 8 * L.max_tiles;
+    L.claim_words = kXcdSlots * (1 + L.max_tiles);
     uint64_t o = 0;
     L.off_ctrl = o;
     o = align_up(o + kSegWords * 4, 256);
