@@ -158,6 +158,45 @@ rs_status rs_profile_read(rs_context *ctx, const char **names, int *tags, float 
                           int *count);
 
 /*
+ * Key orders.  The entry points above sort unsigned keys ascending.  rs_sort
+ * and rs_segmented_sort_order take `order`, a combination of:
+ *   RS_ORDER_SIGNED      keys are two's-complement integers;
+ *   RS_ORDER_FLOAT       keys are IEEE-754 floats (binary32 for 32-bit keys,
+ *                        binary64 for 64-bit keys) ordered as a total order
+ *                        of their bit patterns: -NaN < -inf < ... < -0 <
+ *                        +0 < ... < +inf < +NaN (so -0 sorts before +0 and
+ *                        NaNs sort at the ends by their sign);
+ *   RS_ORDER_DESCENDING  largest first; equal keys keep their input order.
+ * SIGNED and FLOAT exclude each other; 0 is unsigned ascending.  Each order
+ * is an exact bijection of the key bits applied where keys are read and
+ * undone where they are written, inside the same kernels (no extra pass
+ * over the data); output keys are the input keys, reordered.  The sort
+ * stays stable (Section 2.6's counting sorts on the mapped digits).
+ */
+typedef enum {
+    RS_ORDER_UNSIGNED = 0,
+    RS_ORDER_SIGNED = 1,
+    RS_ORDER_FLOAT = 2,
+    RS_ORDER_DESCENDING = 4
+} rs_order;
+
+/*
+ * Stable sort of n keys (vals_in/vals_out both NULL) or key-value pairs of
+ * key_type's width in the given order; otherwise as rs_sort_keys_u32 /
+ * rs_sort_pairs_u32.  Unknown or conflicting order flags ->
+ * RS_ERR_INVALID_ARGUMENT.
+ */
+rs_status rs_sort(rs_context *ctx, rs_key_type key_type, uint32_t order, const void *keys_in,
+                  const void *vals_in, void *keys_out, void *vals_out, uint64_t n, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* rs_segmented_sort with a key order; same arguments otherwise. */
+rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_t order,
+                                  const void *keys_in, const void *vals_in, void *keys_out,
+                                  void *vals_out, const uint64_t *offsets, uint32_t num_segments,
+                                  uint64_t total, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Kernel configurations and the tune table.
  *
  * The digit width r is a free parameter of the method (Section 2.6: the

@@ -102,3 +102,69 @@ def segmented_sort(keys, vals, offsets, r: int = 8):
     if _load().oracle_segmented_sort(bits, _ptr(k), _ptr(v), _ptr(off), off.size - 1, r) != 0:
         raise ValueError("oracle rejected the arguments")
     return k, v
+
+
+# ---------------------------------------------------------------------------
+# Key orders other than unsigned ascending.  Each order is a bijection of the
+# key bits that is monotone from the wanted order to the unsigned order, so
+# the stable unsigned sort of the mapped keys, mapped back, is the stable sort
+# in that order.  Written from the definitions:
+#   signed      two's complement: adding 2^(K-1) (mod 2^K) -- flipping the
+#               sign bit -- turns [-2^(K-1), 2^(K-1)) into [0, 2^K) in order;
+#   float       IEEE 754 totalOrder on the bit patterns: non-negative values
+#               grow with their bit pattern, negative ones shrink, so negative
+#               patterns are complemented and the sign bit of the others set;
+#   descending  complementing reverses the unsigned order; ties keep their
+#               input order because the sort of the complemented keys is
+#               stable.
+
+ORDERS = ("unsigned", "signed", "float")
+
+
+def order_key(keys, order="unsigned", descending=False):
+    """Map unsigned key bit patterns (uint32/uint64) to the sort key."""
+    k = np.asarray(keys)
+    if k.dtype not in (np.uint32, np.uint64):
+        raise TypeError("key bit patterns must be uint32 or uint64")
+    if order not in ORDERS:
+        raise ValueError(f"order must be one of {ORDERS}")
+    sign = k.dtype.type(1) << k.dtype.type(8 * k.dtype.itemsize - 1)
+    if order == "signed":
+        m = k ^ sign
+    elif order == "float":
+        m = np.where((k & sign) != 0, ~k, k | sign).astype(k.dtype)
+    else:
+        m = k.copy()
+    return ~m if descending else m
+
+
+def order_unkey(mapped, order="unsigned", descending=False):
+    """Inverse of order_key."""
+    m = np.asarray(mapped)
+    if descending:
+        m = ~m
+    sign = m.dtype.type(1) << m.dtype.type(8 * m.dtype.itemsize - 1)
+    if order == "signed":
+        return m ^ sign
+    if order == "float":
+        return np.where((m & sign) != 0, m ^ sign, ~m).astype(m.dtype)
+    return m.copy()
+
+
+def sort_ordered(keys, vals=None, order="unsigned", descending=False):
+    """Stable sort of key bit patterns in the given order (values follow)."""
+    keys, vals = _check_pair(keys, vals)
+    k, v = sort(order_key(keys, order, descending), vals)
+    return order_unkey(k, order, descending), v
+
+
+def segmented_sort_ordered(keys, vals, offsets, order="unsigned", descending=False):
+    """segmented_sort in the given order."""
+    keys, vals = _check_pair(keys, vals)
+    mapped = order_key(keys, order, descending)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    k, v = segmented_sort(mapped, vals, off)
+    out = np.array(keys, copy=True)
+    lo, hi = (int(off[0]), int(off[-1])) if off.size else (0, 0)
+    out[lo:hi] = order_unkey(k[lo:hi], order, descending)
+    return out, v

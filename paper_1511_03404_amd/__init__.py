@@ -4,10 +4,13 @@ The binding only marshals arguments: every step of the sort runs in the HIP
 kernels of ``csrc/``.  PyTorch supplies device memory and the current stream.
 If the library has not been built, every call raises; there is no CPU path.
 
-Keys are unsigned.  A 32-bit sort takes ``torch.uint32`` or ``torch.int32``
-tensors, a 64-bit sort ``torch.uint64`` or ``torch.int64``; signed tensors
-are sorted by their bit pattern read as unsigned.  Values have the key's
-width.  All sorts are stable and ascending (paper, Section 2.6).
+A 32-bit sort takes ``torch.uint32``, ``torch.int32`` or ``torch.float32``
+tensors, a 64-bit sort ``torch.uint64``, ``torch.int64`` or ``torch.float64``.
+The order is chosen with ``order``: "unsigned" (the bit pattern read as an
+unsigned integer; the default for integer tensors), "signed" (two's
+complement) or "float" (IEEE total order of the bit patterns; the default
+for float tensors), and ``descending``.  Values have the key's width.  All
+sorts are stable (paper, Section 2.6): equal keys keep their input order.
 """
 from __future__ import annotations
 
@@ -27,6 +30,10 @@ RS_ERR_OUT_OF_MEMORY = 3
 RS_ERR_DEVICE = 4
 RS_KEY_U32 = 0
 RS_KEY_U64 = 1
+RS_ORDER_SIGNED = 1
+RS_ORDER_FLOAT = 2
+RS_ORDER_DESCENDING = 4
+ORDERS = {"unsigned": 0, "signed": RS_ORDER_SIGNED, "float": RS_ORDER_FLOAT}
 MAX_ELEMENTS = 1 << 30
 # sorts up to this many elements run in one workgroup's LDS (one launch),
 # whatever configuration the tune table selects
@@ -38,6 +45,7 @@ EXPORTED = (
     "rs_segmented_sort", "rs_segmented_workspace_bytes", "rs_status_string", "rs_last_error",
     "rs_profile_enable", "rs_profile_tag", "rs_profile_reset", "rs_profile_read",
     "rs_config_count", "rs_config_get", "rs_tune_set", "rs_tune_get",
+    "rs_sort", "rs_segmented_sort_order",
 )
 
 
@@ -94,12 +102,15 @@ def lib():
             L.rs_config_get.argtypes = [ci, ci, ci, ctypes.POINTER(Config)]
             L.rs_tune_set.argtypes = [vp, ci, ci, ci, ci, ci]
             L.rs_tune_get.argtypes = [vp, ci, ci, ci, ci, ctypes.POINTER(ci)]
+            L.rs_sort.argtypes = [vp, ci, u32, vp, vp, vp, vp, u64, vp, sz, vp]
+            L.rs_segmented_sort_order.argtypes = [vp, ci, u32, vp, vp, vp, vp, vp, u32, u64, vp,
+                                                  sz, vp]
             for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
                          "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
                          "rs_segmented_sort", "rs_segmented_workspace_bytes",
                          "rs_profile_enable", "rs_profile_tag", "rs_profile_reset",
                          "rs_profile_read", "rs_config_count", "rs_config_get",
-                         "rs_tune_set", "rs_tune_get"):
+                         "rs_tune_set", "rs_tune_get", "rs_sort", "rs_segmented_sort_order"):
                 getattr(L, name).restype = ci
             _lib = L
     return _lib
@@ -219,13 +230,14 @@ def context(device: int | None = None) -> Context:
     return c
 
 
-_BITS = {torch.uint32: 32, torch.int32: 32, torch.uint64: 64, torch.int64: 64}
+_BITS = {torch.uint32: 32, torch.int32: 32, torch.float32: 32,
+         torch.uint64: 64, torch.int64: 64, torch.float64: 64}
 
 
 def key_bits(t: torch.Tensor) -> int:
     b = _BITS.get(t.dtype)
     if b is None:
-        raise TypeError(f"unsupported key dtype {t.dtype}; use (u)int32 or (u)int64")
+        raise TypeError(f"unsupported dtype {t.dtype}; use (u)int32/float32 or (u)int64/float64")
     return b
 
 
@@ -246,14 +258,24 @@ def _check_tensor(t: torch.Tensor, name: str, bits: int, n: int):
         raise ValueError(f"{name} must be contiguous with {n} elements")
 
 
+def _order_flags(keys: torch.Tensor, order, descending: bool) -> int:
+    if order is None:
+        order = "float" if keys.dtype in (torch.float32, torch.float64) else "unsigned"
+    if order not in ORDERS:
+        raise ValueError(f"order must be one of {sorted(ORDERS)}")
+    return ORDERS[order] | (RS_ORDER_DESCENDING if descending else 0)
+
+
 def _workspace(ctx: Context, nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
 
 
 def sort_keys(keys: torch.Tensor, out: torch.Tensor | None = None, *, ctx: Context | None = None,
-              workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """Ascending stable sort of a 1-D key tensor.  ``out`` may be ``keys``
-    (in place).  Asynchronous on the current stream."""
+              workspace: torch.Tensor | None = None, order: str | None = None,
+              descending: bool = False) -> torch.Tensor:
+    """Stable sort of a 1-D key tensor (ascending unless ``descending``; see
+    the module docstring for ``order``).  ``out`` may be ``keys`` (in
+    place).  Asynchronous on the current stream."""
     bits = key_bits(keys)
     n = keys.numel()
     _check_tensor(keys, "keys", bits, n)
@@ -263,8 +285,14 @@ def sort_keys(keys: torch.Tensor, out: torch.Tensor | None = None, *, ctx: Conte
     ctx = ctx or context(keys.device.index)
     if n == 0:
         return out
+    flags = _order_flags(keys, order, descending)
     need = ctx.workspace_bytes(bits, False, n)
     ws = workspace if workspace is not None else _workspace(ctx, need, keys.device)
+    if flags:
+        kt = RS_KEY_U32 if bits == 32 else RS_KEY_U64
+        _check(lib().rs_sort(ctx.handle, kt, flags, _ptr(keys), None, _ptr(out), None, n,
+                             _ptr(ws), ws.numel(), _stream(ctx.device)))
+        return out
     f = lib().rs_sort_keys_u32 if bits == 32 else lib().rs_sort_keys_u64
     _check(f(ctx.handle, _ptr(keys), _ptr(out), n, _ptr(ws), ws.numel(), _stream(ctx.device)))
     return out
@@ -272,7 +300,8 @@ def sort_keys(keys: torch.Tensor, out: torch.Tensor | None = None, *, ctx: Conte
 
 def sort_pairs(keys: torch.Tensor, values: torch.Tensor, keys_out: torch.Tensor | None = None,
                values_out: torch.Tensor | None = None, *, ctx: Context | None = None,
-               workspace: torch.Tensor | None = None):
+               workspace: torch.Tensor | None = None, order: str | None = None,
+               descending: bool = False):
     """Stable sort of (key, value) pairs by key.  Returns (keys_out, values_out)."""
     bits = key_bits(keys)
     n = keys.numel()
@@ -285,8 +314,14 @@ def sort_pairs(keys: torch.Tensor, values: torch.Tensor, keys_out: torch.Tensor 
     ctx = ctx or context(keys.device.index)
     if n == 0:
         return keys_out, values_out
+    flags = _order_flags(keys, order, descending)
     need = ctx.workspace_bytes(bits, True, n)
     ws = workspace if workspace is not None else _workspace(ctx, need, keys.device)
+    if flags:
+        kt = RS_KEY_U32 if bits == 32 else RS_KEY_U64
+        _check(lib().rs_sort(ctx.handle, kt, flags, _ptr(keys), _ptr(values), _ptr(keys_out),
+                             _ptr(values_out), n, _ptr(ws), ws.numel(), _stream(ctx.device)))
+        return keys_out, values_out
     f = lib().rs_sort_pairs_u32 if bits == 32 else lib().rs_sort_pairs_u64
     _check(f(ctx.handle, _ptr(keys), _ptr(values), _ptr(keys_out), _ptr(values_out), n,
              _ptr(ws), ws.numel(), _stream(ctx.device)))
@@ -295,7 +330,8 @@ def sort_pairs(keys: torch.Tensor, values: torch.Tensor, keys_out: torch.Tensor 
 
 def segmented_sort(keys: torch.Tensor, values: torch.Tensor | None, offsets: torch.Tensor,
                    keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None,
-                   *, ctx: Context | None = None, workspace: torch.Tensor | None = None):
+                   *, ctx: Context | None = None, workspace: torch.Tensor | None = None,
+                   order: str | None = None, descending: bool = False):
     """Sort every segment [offsets[s], offsets[s+1]) on its own, in one batch.
     ``offsets`` is a device int64/uint64 tensor of num_segments + 1 entries."""
     bits = key_bits(keys)
@@ -319,8 +355,9 @@ def segmented_sort(keys: torch.Tensor, values: torch.Tensor | None, offsets: tor
     kt = RS_KEY_U32 if bits == 32 else RS_KEY_U64
     need = ctx.segmented_workspace_bytes(bits, has_v, n, nseg)
     ws = workspace if workspace is not None else _workspace(ctx, need, keys.device)
-    _check(lib().rs_segmented_sort(ctx.handle, kt, _ptr(keys), _ptr(values), _ptr(keys_out),
-                                   _ptr(values_out), _ptr(offsets), nseg, n, _ptr(ws),
-                                   ws.numel(), _stream(ctx.device)))
+    flags = _order_flags(keys, order, descending)
+    _check(lib().rs_segmented_sort_order(ctx.handle, kt, flags, _ptr(keys), _ptr(values),
+                                         _ptr(keys_out), _ptr(values_out), _ptr(offsets), nseg, n,
+                                         _ptr(ws), ws.numel(), _stream(ctx.device)))
     return keys_out, values_out
 

@@ -40,6 +40,7 @@ struct BlockArgs {
     const uint32_t *list_len;
     uint32_t *claim;
     uint64_t n;
+    uint32_t kmap;  // key order (kMap*): applied on load, undone on store
 };
 
 template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS>
@@ -99,6 +100,15 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
             if constexpr (HAS_V)
                 val[j] = pos < m ? vin[start + pos] : (V)0;
         }
+        // mapped once every load is issued (a map between loads would wait
+        // for each in turn); padding keys stay unmapped
+        if (a.kmap) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const K mk = map_in(key[j], a.kmap);
+                key[j] = off0 + j * kWave < m ? mk : key[j];
+            }
+        }
 
         for (int p = 0; p < D; ++p) {
             const int shift = p * kRadixBits;
@@ -149,7 +159,7 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
         for (int j = 0; j < ITEMS; ++j) {
             const uint32_t pos = off0 + j * kWave;
             if (pos < m) {
-                kout[start + pos] = key[j];
+                kout[start + pos] = map_out(key[j], a.kmap);
                 if constexpr (HAS_V)
                     vout[start + pos] = val[j];
             }

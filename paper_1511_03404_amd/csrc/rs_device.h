@@ -21,6 +21,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace rs {
 
@@ -51,6 +52,8 @@ constexpr int kPlanSrcShift = 2;           // buffer id, 2 bits
 constexpr int kPlanDstShift = 4;           // buffer id, 2 bits
 constexpr uint32_t kBufIn = 0, kBufOut = 1, kBufTmp = 2;
 constexpr uint32_t kPlanBallot = 64u;      // skewed digit: rank with ballots, not the LDS table
+constexpr uint32_t kPlanFirst = 128u;      // the first moving pass (reads the input)
+constexpr uint32_t kPlanLast = 256u;       // the last moving pass, writing the output
 
 template <typename K>
 struct KeyTraits;
@@ -66,6 +69,48 @@ struct KeyTraits<uint64_t> {
     static constexpr int kBits = 64;
     static constexpr uint64_t kPad = ~0ull;
 };
+
+// Key orders.  The sort orders unsigned keys; other orders are exact
+// bijections of the key bits applied where keys are read from the input and
+// undone where they are written to the output:
+//   kMapSigned   two's-complement integers: flip the sign bit;
+//   kMapFloat    IEEE floats, total order of the bit patterns (-NaN < -inf <
+//                ... < -0 < +0 < ... < +inf < +NaN): flip every bit of a
+//                negative key, only the sign bit of a positive one;
+//   kMapDescending  after the above, complement the key (equal keys keep
+//                their input order, so the descending sort is stable too).
+constexpr uint32_t kMapSigned = 1u;
+constexpr uint32_t kMapFloat = 2u;
+constexpr uint32_t kMapDescending = 4u;
+
+// Both maps are branch-free: each is one XOR with a mask built from uniform
+// flags and the key's own sign bit, so a tile's loads stay in flight
+// together and the unsigned ascending order costs a few ALU operations.
+template <typename K>
+__device__ __forceinline__ K map_in(K k, uint32_t kmap)
+{
+    using S = std::make_signed_t<K>;
+    constexpr K sign = (K)1 << (KeyTraits<K>::kBits - 1);
+    const K x = (kmap & (kMapSigned | kMapFloat)) ? sign : (K)0;
+    const K f = (kmap & kMapFloat) ? ~(K)0 : (K)0;
+    const K d = (kmap & kMapDescending) ? ~(K)0 : (K)0;
+    const K neg = (K)((S)k >> (KeyTraits<K>::kBits - 1));  // all ones if the top bit is set
+    return k ^ ((x | (f & neg)) ^ d);
+}
+
+template <typename K>
+__device__ __forceinline__ K map_out(K k, uint32_t kmap)
+{
+    using S = std::make_signed_t<K>;
+    constexpr K sign = (K)1 << (KeyTraits<K>::kBits - 1);
+    const K x = (kmap & (kMapSigned | kMapFloat)) ? sign : (K)0;
+    const K f = (kmap & kMapFloat) ? ~(K)0 : (K)0;
+    const K d = (kmap & kMapDescending) ? ~(K)0 : (K)0;
+    k ^= d;
+    // a mapped float with the top bit clear came from a negative key
+    const K pos = (K)((S)k >> (KeyTraits<K>::kBits - 1));
+    return k ^ (x | (f & ~pos));
+}
 
 // Number of R-bit digit positions of a K key (the last one may be narrower).
 template <typename K, int R>

@@ -90,6 +90,7 @@ struct HistArgs {
     uint32_t *hist;       // [d][2^R]
     uint4 *status;        // look-back words of all passes, cleared here
     uint64_t status_vec;  // number of uint4 in status
+    uint32_t kmap;        // key order (kMap*), applied to every key read
 };
 
 // Count one key's D digits into the wave's LDS sub-histograms.
@@ -173,6 +174,11 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
                 key[2 * i + 1] = (K)(((uint64_t)v[i].w << 32) | v[i].z);
             }
         }
+        if (a.kmap) {
+#pragma unroll
+            for (int i = 0; i < NK; ++i)
+                key[i] = map_in(key[i], a.kmap);
+        }
         count_batch<K, R, NK>(sh[w], key);
     }
     // the rest: unaligned head, vectors after the last full batch, ragged
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
     const uint64_t extra = a.head + (a.n - rest0);
     for (uint64_t i = gtid; i < extra; i += gstride) {
         const uint64_t idx = i < a.head ? i : rest0 + (i - a.head);
-        count_one<K, R>(sh[w], keys[idx]);
+        count_one<K, R>(sh[w], map_in(keys[idx], a.kmap));
     }
     __syncthreads();
 
@@ -262,7 +268,8 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
                 else
                     dst = ((q_total - 1 - q) & 1) ? kBufTmp : kBufOut;
                 plan = kPlanRun | (prev << kPlanSrcShift) | (dst << kPlanDstShift) |
-                       (s_skewed[p] ? kPlanBallot : 0u);
+                       (s_skewed[p] ? kPlanBallot : 0u) | (q == 0 ? kPlanFirst : 0u) |
+                       (q == q_total - 1 && dst == kBufOut ? kPlanLast : 0u);
                 prev = dst;
                 ++q;
             }
@@ -288,6 +295,7 @@ struct PassArgs {
     uint32_t *claims;            // per-XCD claim counters and group lists
     uint32_t num_tiles;
     uint32_t num_groups;
+    uint32_t kmap;  // key order (kMap*), 0 = unsigned ascending
 };
 
 // Which compute die (XCD) this wave runs on, from the XCC_ID hardware register.
@@ -399,9 +407,12 @@ __device__ __forceinline__ void store_at(T *p, uint32_t i, T v)
         p[i] = v;
 }
 
+// Load a tile's keys (mapped to the sort order with kmap) and values;
+// positions past `valid` get padding keys that sort after every real key.
 template <typename K, typename V, bool HAS_V, int ITEMS>
 __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t valid, uint32_t off0,
-                                          K (&key)[ITEMS], V (&val)[HAS_V ? ITEMS : 1], bool full)
+                                          K (&key)[ITEMS], V (&val)[HAS_V ? ITEMS : 1], bool full,
+                                          uint32_t kmap)
 {
     if (full) {
 #pragma unroll
@@ -412,6 +423,13 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
             for (int j = 0; j < ITEMS; ++j)
                 val[j] = tv[off0 + j * kWave];
         }
+        // mapped after every load is issued, and not at all in the unsigned
+        // ascending order: the loads stay in flight together
+        if (kmap) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                key[j] = map_in(key[j], kmap);
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j)
@@ -420,6 +438,13 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j)
                 val[j] = off0 + j * kWave < valid ? tv[off0 + j * kWave] : (V)0;
+        }
+        if (kmap) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const K mk = map_in(key[j], kmap);
+                key[j] = off0 + j * kWave < valid ? mk : key[j];
+            }
         }
     }
 }
@@ -457,7 +482,8 @@ template <typename K, typename V, bool HAS_V, typename C>
 __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V *tv, K *dk,
                                           V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
                                           uint32_t first_tile, uint32_t *status, uint32_t dbase,
-                                          int shift, bool ballot_rank)
+                                          int shift, bool ballot_rank, uint32_t map_load,
+                                          uint32_t map_store)
 {
     constexpr int R = C::kRadixBits;
     constexpr uint32_t NB = C::kBins;
@@ -479,7 +505,7 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
     // load: item j of lane l is element j*64 + l of this wave's run
     K key[ITEMS];
     V val[HAS_V ? ITEMS : 1];
-    load_tile<K, V, HAS_V, ITEMS>(tk, tv, valid, off0, key, val, valid == (uint32_t)T);
+    load_tile<K, V, HAS_V, ITEMS>(tk, tv, valid, off0, key, val, valid == (uint32_t)T, map_load);
 
     // count: stable rank of every item among the wave's items of its digit
     uint32_t rank[ITEMS];
@@ -563,7 +589,7 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
         const K k = s_k[pos];
         dst[i] = L.gbase[digit_of<R>(k, shift)] + pos;
         if (dst[i] < limit)
-            store_at(dk, dst[i], k);
+            store_at(dk, dst[i], map_out(k, map_store));
     }
     if constexpr (HAS_V) {
         __syncthreads();
@@ -623,7 +649,9 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
         const uint64_t tb = (uint64_t)tile * T;
         const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tb);
         pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile,
-                                  0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0);
+                                  0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0,
+                                  (plan & kPlanFirst) ? a.kmap : 0u,
+                                  (plan & kPlanLast) ? a.kmap : 0u);
     }
 }
 
@@ -641,6 +669,7 @@ struct SegHistArgs {
     uint32_t *ctrl;
     uint32_t *seg_hist;  // [large segment][d][2^R], zeroed
     uint32_t *seg_base;  // [large segment][d][2^R]
+    uint32_t kmap;       // key order applied to every key read
 };
 
 template <typename K, int R>
@@ -675,7 +704,7 @@ __global__ __launch_bounds__(256) void k_seg_hist(SegHistArgs a)
         const uint32_t len = rec.size > lo ? (uint32_t)min<uint64_t>(kSegChunk, rec.size - lo) : 0u;
         const K *sk = keys + rec.start + lo;
         for (uint32_t i = t; i < len; i += 256) {
-            const K key = sk[i];
+            const K key = map_in(sk[i], a.kmap);
             const uint64_t active = __ballot(1);  // before any branch narrows it
 #pragma unroll
             for (int p = 0; p < D; ++p) {
@@ -752,6 +781,8 @@ struct SegPassArgs {
     int pass;
     int shift;
     int d;
+    uint32_t map_load;   // key order applied to the keys read (first pass)
+    uint32_t map_store;  // key order undone on the keys written (last pass into the output)
 };
 
 template <typename K, typename V, bool HAS_V, typename C>
@@ -787,7 +818,8 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
                                   HAS_V ? (const V *)a.src_v + off : nullptr,
                                   (K *)a.dst_k + rec.start,
                                   HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
-                                  tile, rec.tile_start, a.status, dbase, a.shift, false);
+                                  tile, rec.tile_start, a.status, dbase, a.shift, false,
+                                  a.map_load, a.map_store);
     }
 }
 
@@ -803,6 +835,7 @@ struct SegCopyArgs {
     const uint32_t *ctrl;  // segmented control block
     uint32_t max_tiles;
     uint32_t tile;  // elements per tile
+    uint32_t kmap;  // key order undone on the keys copied out
 };
 
 template <typename K, bool HAS_V>
@@ -815,8 +848,15 @@ __global__ __launch_bounds__(256) void k_seg_copy(SegCopyArgs a)
         if (lo >= rec.size)
             continue;
         const uint64_t hi = std::min<uint64_t>(lo + a.tile, rec.size);
-        copy_range((const K *)a.src_k + rec.start, (K *)a.dst_k + rec.start, lo, hi, threadIdx.x,
-                   256);
+        if (a.kmap) {
+            const K *sk = (const K *)a.src_k + rec.start;
+            K *dk = (K *)a.dst_k + rec.start;
+            for (uint64_t i = lo + threadIdx.x; i < hi; i += 256)
+                dk[i] = map_out(sk[i], a.kmap);
+        } else {
+            copy_range((const K *)a.src_k + rec.start, (K *)a.dst_k + rec.start, lo, hi,
+                       threadIdx.x, 256);
+        }
         if constexpr (HAS_V)
             copy_range((const K *)a.src_v + rec.start, (K *)a.dst_v + rec.start, lo, hi,
                        threadIdx.x, 256);

@@ -56,7 +56,7 @@ __global__ void k_zero(uint4 *p, uint64_t n)
 // k_finalize: in-place sort with an odd number of moving passes.
 
 template <typename K, typename V, bool HAS_V>
-__global__ void k_finalize(Bufs b, uint32_t n, const uint32_t *ctrl)
+__global__ void k_finalize(Bufs b, uint32_t n, const uint32_t *ctrl, uint32_t kmap)
 {
     if (ctrl[kCtrlFinal] != 1u)
         return;
@@ -64,7 +64,7 @@ __global__ void k_finalize(Bufs b, uint32_t n, const uint32_t *ctrl)
     K *ok = (K *)b.out_k;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        ok[i] = tk[i];
+        ok[i] = map_out(tk[i], kmap);
         if constexpr (HAS_V)
             ((V *)b.out_v)[i] = ((const V *)b.tmp_v)[i];
     }
@@ -358,7 +358,7 @@ static const char *pass_name()
 
 template <typename K, bool HAS_V>
 static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, K *vout,
-                          uint64_t n, void *ws, size_t ws_bytes, void *stream)
+                          uint64_t n, void *ws, size_t ws_bytes, void *stream, uint32_t kmap = 0)
 {
     if (!ctx)
         return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
@@ -375,7 +375,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     using B = BlockShape<K, HAS_V>;
     if (n <= (uint64_t)B::kMediumCap) {
         // the whole array fits one workgroup's LDS: one launch, all passes
-        BlockArgs ba{kin, vin, kout, vout, nullptr, nullptr, nullptr, n};
+        BlockArgs ba{kin, vin, kout, vout, nullptr, nullptr, nullptr, n, kmap};
         if (n <= (uint64_t)B::kSmallCap) {
             launch(ctx, s, "k_block_sort_small", [&] {
                 hipLaunchKernelGGL((k_block_sort<K, K, HAS_V, B::kSmallThreads, B::kItems>),
@@ -417,6 +417,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     ha.head = (uint32_t)std::min<uint64_t>(n, mis ? (16 / sizeof(K)) - mis : 0);
     ha.nvec = (uint32_t)((n - ha.head) / (16 / sizeof(K)));
     ha.hist = hist;
+    ha.kmap = kmap;
     ha.status = (uint4 *)status;
     ha.status_vec = L.status_bytes / 16;
     const uint64_t hist_blocks = std::max<uint64_t>(
@@ -447,13 +448,14 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         pa.claims = status + (uint64_t)L.d * L.tiles * L.bins + (uint64_t)p * L.claim_words;
         pa.num_tiles = (uint32_t)L.tiles;
         pa.num_groups = (uint32_t)((L.tiles + kClaimGroup - 1) / kClaimGroup);
+        pa.kmap = kmap;
         launch(ctx, s, pass_name<K, HAS_V>(), [&] { op.pass(pa, pass_grid, s); });
     }
     if (in_place) {
         const uint32_t blocks = (uint32_t)std::min<uint64_t>(4096, (n + 255) / 256);
         launch(ctx, s, "k_finalize", [&] {
             hipLaunchKernelGGL((k_finalize<K, K, HAS_V>), dim3(blocks), dim3(256), 0, s, b,
-                               (uint32_t)n, (const uint32_t *)ctrl);
+                               (uint32_t)n, (const uint32_t *)ctrl, kmap);
         });
     }
     hipError_t e = hipGetLastError();
@@ -521,7 +523,7 @@ static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total,
 template <typename K, bool HAS_V>
 static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin, void *kout,
                                void *vout, const uint64_t *offsets, uint32_t nseg, uint64_t total,
-                               void *ws, size_t ws_bytes, void *stream)
+                               void *ws, size_t ws_bytes, void *stream, uint32_t kmap = 0)
 {
     if (!ctx)
         return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
@@ -606,7 +608,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     };
     {
         BlockArgs ba{kin, vin, kout, vout, small_list, ctrl + kSegSmallLen, ctrl + kSegSmallClaim,
-                     0};
+                     0, kmap};
         auto kern = k_block_sort<K, K, HAS_V, B::kSmallThreads, B::kItems>;
         const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, B::kSmallThreads), nseg);
         launch(ctx, s, "k_block_sort_small", [&] {
@@ -615,7 +617,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     }
     {
         BlockArgs ba{kin, vin, kout, vout, medium_list, ctrl + kSegMediumLen,
-                     ctrl + kSegMediumClaim, 0};
+                     ctrl + kSegMediumClaim, 0, kmap};
         auto kern = k_block_sort<K, K, HAS_V, B::kMediumThreads, B::kItems>;
         const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, B::kMediumThreads), nseg);
         launch(ctx, s, "k_block_sort_medium", [&] {
@@ -628,7 +630,8 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     // pass may not write its own input) with an odd d, the passes start in
     // the scratch copy and the large segments are copied back at the end.
     {
-        SegHistArgs ha{kin, large, chunk_seg, (uint32_t)L.max_chunks, ctrl, seg_hist, seg_base};
+        SegHistArgs ha{kin, large, chunk_seg, (uint32_t)L.max_chunks, ctrl, seg_hist, seg_base,
+                       kmap};
         const uint32_t g = std::min<uint64_t>(grid_of(op.hist_kernel, 256), L.max_chunks);
         launch(ctx, s, "k_seg_hist", [&] { op.hist(ha, g, s); });
         const uint32_t gs = std::min<uint32_t>(grid_of(op.scan_kernel, 256), nseg);
@@ -656,6 +659,8 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
             pa.pass = p;
             pa.shift = p * op.r;
             pa.d = L.d;
+            pa.map_load = p == 0 ? kmap : 0u;
+            pa.map_store = (p == L.d - 1 && to_out) ? kmap : 0u;
             launch(ctx, s, sizeof(K) == 4 ? "k_seg_pass_u32" : "k_seg_pass_u64",
                    [&] { op.pass(pa, g, s); });
             src_k = pa.dst_k;
@@ -664,7 +669,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     }
     if (copy_back) {
         SegCopyArgs cp{tmp_k, tmp_v, kout, vout, large, tile_seg, ctrl, (uint32_t)L.max_tiles,
-                       (uint32_t)op.tile};
+                       (uint32_t)op.tile, kmap};
         const uint32_t g = (uint32_t)std::min<uint64_t>(L.max_tiles, 4096);
         launch(ctx, s, "k_seg_copy", [&] {
             hipLaunchKernelGGL((k_seg_copy<K, HAS_V>), dim3(g), dim3(256), 0, s, cp);
@@ -805,6 +810,75 @@ rs_status rs_sort_pairs_u64(rs_context *ctx, const uint64_t *keys_in, const uint
 {
     return run_sort<uint64_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, n, ws, ws_bytes,
                                     stream);
+}
+
+static uint32_t order_map(rs_key_type key_type, uint32_t order, rs_status *st)
+{
+    *st = RS_OK;
+    if (order & ~(uint32_t)(RS_ORDER_SIGNED | RS_ORDER_FLOAT | RS_ORDER_DESCENDING)) {
+        *st = fail(RS_ERR_INVALID_ARGUMENT, "unknown order flags 0x%x", order);
+        return 0;
+    }
+    if ((order & RS_ORDER_SIGNED) && (order & RS_ORDER_FLOAT)) {
+        *st = fail(RS_ERR_INVALID_ARGUMENT, "RS_ORDER_SIGNED and RS_ORDER_FLOAT exclude each other");
+        return 0;
+    }
+    if (key_type != RS_KEY_U32 && key_type != RS_KEY_U64) {
+        *st = fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+        return 0;
+    }
+    return ((order & RS_ORDER_SIGNED) ? kMapSigned : 0u) | ((order & RS_ORDER_FLOAT) ? kMapFloat : 0u) |
+           ((order & RS_ORDER_DESCENDING) ? kMapDescending : 0u);
+}
+
+rs_status rs_sort(rs_context *ctx, rs_key_type key_type, uint32_t order, const void *keys_in,
+                  const void *vals_in, void *keys_out, void *vals_out, uint64_t n, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    rs_status st;
+    const uint32_t kmap = order_map(key_type, order, &st);
+    if (st != RS_OK)
+        return st;
+    if ((vals_in != nullptr) != (vals_out != nullptr))
+        return fail(RS_ERR_INVALID_ARGUMENT, "vals_in and vals_out must both be given or both NULL");
+    if (key_type == RS_KEY_U32) {
+        if (vals_in)
+            return run_sort<uint32_t, true>(ctx, (const uint32_t *)keys_in, (const uint32_t *)vals_in,
+                                            (uint32_t *)keys_out, (uint32_t *)vals_out, n, ws,
+                                            ws_bytes, stream, kmap);
+        return run_sort<uint32_t, false>(ctx, (const uint32_t *)keys_in, nullptr,
+                                         (uint32_t *)keys_out, nullptr, n, ws, ws_bytes, stream,
+                                         kmap);
+    }
+    if (vals_in)
+        return run_sort<uint64_t, true>(ctx, (const uint64_t *)keys_in, (const uint64_t *)vals_in,
+                                        (uint64_t *)keys_out, (uint64_t *)vals_out, n, ws, ws_bytes,
+                                        stream, kmap);
+    return run_sort<uint64_t, false>(ctx, (const uint64_t *)keys_in, nullptr, (uint64_t *)keys_out,
+                                     nullptr, n, ws, ws_bytes, stream, kmap);
+}
+
+rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_t order,
+                                  const void *keys_in, const void *vals_in, void *keys_out,
+                                  void *vals_out, const uint64_t *offsets, uint32_t num_segments,
+                                  uint64_t total, void *ws, size_t ws_bytes, void *stream)
+{
+    rs_status st;
+    const uint32_t kmap = order_map(key_type, order, &st);
+    if (st != RS_OK)
+        return st;
+    if (key_type == RS_KEY_U32) {
+        if (vals_in || vals_out)
+            return run_segmented<uint32_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                                 num_segments, total, ws, ws_bytes, stream, kmap);
+        return run_segmented<uint32_t, false>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                              num_segments, total, ws, ws_bytes, stream, kmap);
+    }
+    if (vals_in || vals_out)
+        return run_segmented<uint64_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                             num_segments, total, ws, ws_bytes, stream, kmap);
+    return run_segmented<uint64_t, false>(ctx, keys_in, vals_in, keys_out, vals_out, offsets,
+                                          num_segments, total, ws, ws_bytes, stream, kmap);
 }
 
 rs_status rs_segmented_workspace_bytes(const rs_context *ctx, rs_key_type key_type,

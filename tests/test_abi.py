@@ -111,7 +111,7 @@ def test_python_binding_rejects_host_tensors(rs):
     with pytest.raises(ValueError):
         rs.sort_keys(torch.zeros(4, dtype=torch.int32))
     with pytest.raises(TypeError):
-        rs.key_bits(torch.zeros(4, dtype=torch.float32))
+        rs.key_bits(torch.zeros(4, dtype=torch.float16))
 
 
 def test_compiled_configurations(rs):
@@ -187,3 +187,33 @@ def test_tune_cache_round_trip(rs, ctx, tmp_path):
     assert tune.load(str(path), ctx) == 1
     assert ctx.tune_get(64, False, True, 30) == 3
     assert ctx.tune_get(64, False, True, 29) == 0
+
+
+def test_order_flag_errors(rs, ctx):
+    """rs_sort and rs_segmented_sort_order reject contradictory or unknown
+    order flags before any HIP call; the Python binding rejects unknown
+    order names."""
+    import torch
+    L = rs.lib()
+    fake = 0x7F0000000000
+    need = ctx.workspace_bytes(32, False, 1000)
+    ws = fake + (1 << 34)
+    flags = rs.RS_ORDER_SIGNED | rs.RS_ORDER_FLOAT
+    assert L.rs_sort(ctx.handle, 0, flags, fake, None, fake + 8192, None, 1000, ws, need,
+                     None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"exclude" in L.rs_last_error()
+    assert L.rs_sort(ctx.handle, 0, 8, fake, None, fake + 8192, None, 1000, ws, need,
+                     None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"unknown order" in L.rs_last_error()
+    assert L.rs_sort(ctx.handle, 0, rs.RS_ORDER_DESCENDING, None, None, None, None, 0, None, 0,
+                     None) == rs.RS_OK
+    assert L.rs_sort(ctx.handle, 5, 0, fake, None, fake + 8192, None, 1000, ws, need,
+                     None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_segmented_sort_order(ctx.handle, 0, 16, fake, None, fake + 8192, None,
+                                     fake + 65536, 1, 1000, ws, need, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    with pytest.raises(ValueError):
+        rs._order_flags(torch.empty(4, dtype=torch.int32), "reversed", False)
+    assert rs._order_flags(torch.empty(4, dtype=torch.float32), None, True) \
+        == rs.RS_ORDER_FLOAT | rs.RS_ORDER_DESCENDING
+    assert rs._order_flags(torch.empty(4, dtype=torch.int64), None, False) == 0

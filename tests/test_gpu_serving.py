@@ -20,13 +20,13 @@ def rs():
     return rs
 
 
-def make(num, seed, hi_log2=18):
+def make(num, seed, hi_log2=18, rate_per_s=2000.0):
     from paper_1511_03404_amd.serving import Request
     pool = torch.from_numpy(datagen.MT19937(seed).u64(1 << 20)).cuda()
     idx32 = torch.arange(1 << hi_log2, dtype=torch.int64, device="cuda").to(torch.uint32)
     idx64 = torch.arange(1 << hi_log2, dtype=torch.int64, device="cuda").to(torch.uint64)
     reqs = []
-    for q in datagen.requests(num, rate_per_s=2000.0, lo_log2=10, hi_log2=hi_log2, seed=seed):
+    for q in datagen.requests(num, rate_per_s=rate_per_s, lo_log2=10, hi_log2=hi_log2, seed=seed):
         n, bits = q["n"], q["bits"]
         if bits == 32:
             src = pool.view(torch.uint32)
@@ -44,7 +44,10 @@ def make(num, seed, hi_log2=18):
 def test_each_result_same_alone_and_in_the_mix(rs, open_loop):
     import time
     from paper_1511_03404_amd.serving import HipBackend, Scheduler, serve
-    reqs = make(120, seed=3)
+    # open loop: 120 arrivals within about 120 us, faster than three slots
+    # drain them, so later arrivals queue and share batches whatever the
+    # speed of the sort (at a rate the GPU keeps up with, nothing would queue)
+    reqs = make(120, seed=3, rate_per_s=1e6 if open_loop else 2000.0)
     be = HipBackend(slots=3, max_batch_requests=16)
     sch = Scheduler(be, mem_cap=1 << 30, slots=3, max_batch_elems=1 << 19,
                     max_batch_requests=16)
