@@ -4,9 +4,11 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product path (the HIP library in
 ``paper_1511_03404_amd``) never loads it and shares no code with it.
 
-The arithmetic lives in ``lsd_oracle.c`` (plain C, compiled with gcc): a
+The arithmetic lives in plain C compiled with gcc: ``lsd_oracle.c``, a
 stable counting-sort LSD radix sort written from the paper's description
-(Section 2.6).  This module only marshals numpy arrays into it.
+(Section 2.6), and ``merge_oracle.c``, the stable merge sort of Section 2.4.
+This module only marshals numpy arrays into them (and holds the key-order
+maps, written in numpy from their definitions).
 """
 from __future__ import annotations
 
@@ -17,7 +19,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "lsd_oracle.c")
+_SRCS = [os.path.join(_HERE, "lsd_oracle.c"), os.path.join(_HERE, "merge_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -27,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared",
-                               "-fPIC", _SRC, "-o", tmp])
+                               "-fPIC", *_SRCS, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -43,8 +45,9 @@ def _load():
         lib.oracle_sort_u64.argtypes = [vp, vp, u64, ci, ci]
         lib.oracle_digit_histograms.argtypes = [vp, u64, ci, ci, vp]
         lib.oracle_segmented_sort.argtypes = [ci, vp, vp, vp, u64, ci]
+        lib.oracle_merge_sort.argtypes = [ci, vp, vp, u64, u64, ci]
         for f in (lib.oracle_sort_u32, lib.oracle_sort_u64, lib.oracle_digit_histograms,
-                  lib.oracle_segmented_sort):
+                  lib.oracle_segmented_sort, lib.oracle_merge_sort):
             f.restype = ci
         _lib = lib
     return _lib
@@ -104,6 +107,20 @@ def segmented_sort(keys, vals, offsets, r: int = 8):
     return k, v
 
 
+def merge_sort(keys, vals=None, tile: int = 1, levels: int = -1):
+    """Stable merge sort by unsigned key (paper, Section 2.4): runs of ``tile``
+    elements sorted by insertion, then merged pairwise level by level.
+    ``levels`` < 0 runs every level; otherwise returns the state after that
+    many merge levels (runs of tile * 2^levels elements sorted)."""
+    keys, vals = _check_pair(keys, vals)
+    k = np.array(keys, copy=True, order="C")
+    v = None if vals is None else np.array(vals, copy=True, order="C")
+    bits = 32 if k.dtype == np.uint32 else 64
+    if _load().oracle_merge_sort(bits, _ptr(k), _ptr(v), k.size, tile, levels) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return k, v
+
+
 # ---------------------------------------------------------------------------
 # Key orders other than unsigned ascending.  Each order is a bijection of the
 # key bits that is monotone from the wanted order to the unsigned order, so
@@ -155,6 +172,13 @@ def sort_ordered(keys, vals=None, order="unsigned", descending=False):
     """Stable sort of key bit patterns in the given order (values follow)."""
     keys, vals = _check_pair(keys, vals)
     k, v = sort(order_key(keys, order, descending), vals)
+    return order_unkey(k, order, descending), v
+
+
+def merge_sort_ordered(keys, vals=None, order="unsigned", descending=False, tile: int = 1):
+    """merge_sort in the given order."""
+    keys, vals = _check_pair(keys, vals)
+    k, v = merge_sort(order_key(keys, order, descending), vals, tile)
     return order_unkey(k, order, descending), v
 
 
