@@ -9,8 +9,10 @@ Reported: whole-job Mkeys/s, the HBM roofline of the dominant kernel (the
 digit pass) measured with HIP events on the library's launch stream, and the
 CPU oracle's rate on a bounded sample.
 
-Other workloads (``--workload``): u64_keys / u64_pairs (2^25 64-bit), and
-u32_keys_small (2^20 32-bit keys).  Prints ONE JSON line.
+Other workloads (``--workload``): u64_keys / u64_pairs (2^25 64-bit),
+u32_keys_small (2^20 32-bit keys), segmented, serving, grid, and merge (the
+stable merge sort on the same inputs, ``--merge-kind``).  Prints ONE JSON
+line.
 """
 from __future__ import annotations
 
@@ -122,7 +124,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="u32_pairs",
-                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented", "serving", "grid"])
+                    choices=sorted(WORKLOADS) + ["copy_calib", "segmented", "serving", "grid",
+                                                 "merge"])
     ap.add_argument("--dists", default="all",
                     help="comma list of distributions, or 'all' for the six")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -142,6 +145,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=100000,
                     help="serving workload: number of requests per load level")
     ap.add_argument("--slots", type=int, default=4, help="serving workload: streams")
+    ap.add_argument("--merge-kind", default="u32_pairs", choices=sorted(WORKLOADS),
+                    help="merge workload: the kind and size of the radix workload of that name")
     ap.add_argument("--grid-max-log2", type=int, default=25,
                     help="grid workload: largest log2 size (64-bit kinds stop one lower)")
     ap.add_argument("--grid-oracle-max-log2", type=int, default=22,
@@ -443,6 +448,101 @@ def bench_segmented(args, torch, rs, datagen, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_merge(args, torch, rs, datagen, dev):
+    """The stable merge sort (paper, Section 2.4) on the inputs of a radix
+    workload: one sort per distribution per step, inputs resident, HIP-event
+    timing of every kernel; the roofline is that of the merge pass, which
+    reads and writes every element once per merge level."""
+    import oracle
+    n, bits, has_v, wdesc = WORKLOADS[args.merge_kind]
+    dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")
+    kb = bits // 8
+    vb = kb if has_v else 0
+    ins = []
+    for d in dists:
+        k = torch.from_numpy(datagen.keys(d, n, bits, seed=1)).to(dev)
+        v = torch.from_numpy(datagen.values(n, bits)).to(dev) if has_v else None
+        ins.append((d, k, v))
+    ko = torch.empty(n, dtype=ins[0][1].dtype, device=dev)
+    vo = torch.empty(n, dtype=ins[0][1].dtype, device=dev) if has_v else None
+    ctx = rs.context(0)
+    ws = torch.empty(ctx.merge_workspace_bytes(bits, has_v, n), dtype=torch.uint8, device=dev)
+
+    def step():
+        for i, (d, k, v) in enumerate(ins):
+            ctx.profile_tag(i)
+            rs.merge_sort(k, v, ko, vo, ctx=ctx, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile_enable(False)
+    recs = ctx.profile_read()
+    per = {}
+    for i, d in enumerate(dists):
+        kern = {}
+        for name, tag, ms in recs:
+            if tag == i:
+                kern.setdefault(name, []).append(ms)
+        sort_ms = sum(sum(v) for v in kern.values()) / args.steps
+        per[d] = {"ms_per_sort": round(sort_ms, 4), "Mkeys_s": round(n / sort_ms / 1e3, 1),
+                  "kernels_ms": {k: round(sum(v) / args.steps, 4) for k, v in kern.items()}}
+    pass_name = f"k_merge_pass_u{bits}_{'pairs' if has_v else 'keys'}"
+    ref = dists.index("uniform") if "uniform" in dists else 0
+    pass_ms = [ms for name, tag, ms in recs if tag == ref and name == pass_name]
+    roofline = None
+    if pass_ms:
+        avg = sum(pass_ms) / len(pass_ms)
+        bytes_per_launch = 2 * n * (kb + vb)  # one merge level reads and writes everything
+        achieved = bytes_per_launch / (avg * 1e-3) / 1e9
+        t = "unsigned int" if bits == 32 else "unsigned long"
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": pass_name,
+                    "kernel_instance": f"void rs::k_merge_pass<{t}, {t}, "
+                                       f"{'true' if has_v else 'false'}, 256, 16>",
+                    "avg_launch_ms": round(avg, 5), "launches": len(pass_ms),
+                    "bytes_per_launch": bytes_per_launch, "input": dists[ref]}
+    levels = 0
+    while (8192 << levels) < n:
+        levels += 1
+    out = {
+        "metric": "Mkeys/s (stable merge sort)", "value": round(n * len(dists) * args.steps /
+                                                                 elapsed / 1e6, 1),
+        "unit": "Mkeys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"u{bits}", "data": "synthetic",
+        "config": {"workload": f"merge sort of {wdesc}; one sort per distribution per step "
+                               f"({', '.join(dists)}); MT19937 seed 1; tiles of 8192 sorted "
+                               f"in LDS, then {levels} merge levels",
+                   "n": n, "key_bits": bits, "value_bits": bits if has_v else 0,
+                   "distributions": dists, "merge_levels": levels},
+        "roofline": roofline, "per_distribution": per,
+    }
+    if not args.no_cpu_baseline:
+        m = 1 << min(args.cpu_sample_log2, n.bit_length() - 1, 24)
+        tot = 0.0
+        for d in dists:
+            k = datagen.keys(d, m, bits, seed=1)
+            v = datagen.values(m, bits) if has_v else None
+            t0 = time.perf_counter()
+            oracle.merge_sort(k, v)
+            tot += time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(len(dists) * m / tot / 1e6, 3), "unit": "Mkeys/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's merge sort, one sort per distribution "
+                                         f"at n=2^{m.bit_length() - 1}, one thread, {tot:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(bits, has_v, dists, sample_log2):
     """The oracle, as it stands, on a bounded sample of the same workload:
     one sort per distribution at n = 2^sample_log2 (single thread)."""
@@ -506,6 +606,9 @@ def main():
         return
     if args.workload == "grid":
         bench_grid(args, torch, rs, datagen, dev)
+        return
+    if args.workload == "merge":
+        bench_merge(args, torch, rs, datagen, dev)
         return
     n, bits, has_v, wdesc = WORKLOADS[args.workload]
     dists = list(datagen.DISTRIBUTIONS) if args.dists == "all" else args.dists.split(",")

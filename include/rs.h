@@ -197,6 +197,31 @@ rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_
                                   uint64_t total, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Stable merge sort (Section 2.4: the sequence is cut into runs, each run is
+ * sorted, and sorted runs are merged pairwise with a stable merge until one
+ * run remains), the comparison-based counterpart of the radix sort.  Same
+ * result as rs_sort with the same arguments: the unique stable sort in the
+ * given order (position i holds the pair with the i-th smallest key,
+ * equal keys in input order).
+ *
+ * On the device: tiles of 8192 elements are sorted in one workgroup's LDS
+ * (a stable odd-even transposition network per thread, then merge-path
+ * merges in LDS), then ceil(log2(n / 8192)) merge levels each read and
+ * write every element once.  keys_in may equal keys_out (and vals_in
+ * vals_out): in place.  ws: a device buffer of at least
+ * rs_merge_workspace_bytes() bytes (scratch copies of keys and values and
+ * one split word per 4096 outputs), 256-byte aligned, or NULL for the
+ * context's own; n <= 8192 needs none.  Errors as rs_sort.
+ */
+rs_status rs_merge_sort(rs_context *ctx, rs_key_type key_type, uint32_t order,
+                        const void *keys_in, const void *vals_in, void *keys_out, void *vals_out,
+                        uint64_t n, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of workspace rs_merge_sort needs for n elements of this kind. */
+rs_status rs_merge_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int has_values,
+                                   uint64_t n, size_t *bytes);
+
+/*
  * Kernel configurations and the tune table.
  *
  * The digit width r is a free parameter of the method (Section 2.6: the

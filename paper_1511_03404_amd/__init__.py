@@ -11,6 +11,7 @@ unsigned integer; the default for integer tensors), "signed" (two's
 complement) or "float" (IEEE total order of the bit patterns; the default
 for float tensors), and ``descending``.  Values have the key's width.  All
 sorts are stable (paper, Section 2.6): equal keys keep their input order.
+``merge_sort`` gives the same result by the stable merge sort of Section 2.4.
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ EXPORTED = (
     "rs_segmented_sort", "rs_segmented_workspace_bytes", "rs_status_string", "rs_last_error",
     "rs_profile_enable", "rs_profile_tag", "rs_profile_reset", "rs_profile_read",
     "rs_config_count", "rs_config_get", "rs_tune_set", "rs_tune_get",
-    "rs_sort", "rs_segmented_sort_order",
+    "rs_sort", "rs_segmented_sort_order", "rs_merge_sort", "rs_merge_workspace_bytes",
 )
 
 
@@ -105,12 +106,15 @@ def lib():
             L.rs_sort.argtypes = [vp, ci, u32, vp, vp, vp, vp, u64, vp, sz, vp]
             L.rs_segmented_sort_order.argtypes = [vp, ci, u32, vp, vp, vp, vp, vp, u32, u64, vp,
                                                   sz, vp]
+            L.rs_merge_sort.argtypes = [vp, ci, u32, vp, vp, vp, vp, u64, vp, sz, vp]
+            L.rs_merge_workspace_bytes.argtypes = [vp, ci, ci, u64, ctypes.POINTER(sz)]
             for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
                          "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
                          "rs_segmented_sort", "rs_segmented_workspace_bytes",
                          "rs_profile_enable", "rs_profile_tag", "rs_profile_reset",
                          "rs_profile_read", "rs_config_count", "rs_config_get",
-                         "rs_tune_set", "rs_tune_get", "rs_sort", "rs_segmented_sort_order"):
+                         "rs_tune_set", "rs_tune_get", "rs_sort", "rs_segmented_sort_order",
+                         "rs_merge_sort", "rs_merge_workspace_bytes"):
                 getattr(L, name).restype = ci
             _lib = L
     return _lib
@@ -148,6 +152,13 @@ class Context:
         out = ctypes.c_size_t()
         kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
         _check(lib().rs_workspace_bytes(self.handle, kt, int(has_values), n, ctypes.byref(out)))
+        return out.value
+
+    def merge_workspace_bytes(self, key_bits: int, has_values: bool, n: int) -> int:
+        out = ctypes.c_size_t()
+        kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
+        _check(lib().rs_merge_workspace_bytes(self.handle, kt, int(has_values), n,
+                                              ctypes.byref(out)))
         return out.value
 
     def segmented_workspace_bytes(self, key_bits: int, has_values: bool, total: int,
@@ -361,3 +372,34 @@ def segmented_sort(keys: torch.Tensor, values: torch.Tensor | None, offsets: tor
                                          _ptr(ws), ws.numel(), _stream(ctx.device)))
     return keys_out, values_out
 
+
+def merge_sort(keys: torch.Tensor, values: torch.Tensor | None = None,
+               keys_out: torch.Tensor | None = None, values_out: torch.Tensor | None = None, *,
+               ctx: Context | None = None, workspace: torch.Tensor | None = None,
+               order: str | None = None, descending: bool = False):
+    """Stable merge sort (the comparison-based counterpart of sort_keys /
+    sort_pairs, same result).  Returns keys_out, or (keys_out, values_out)
+    when values are given.  Asynchronous on the current stream."""
+    bits = key_bits(keys)
+    n = keys.numel()
+    _check_tensor(keys, "keys", bits, n)
+    has_v = values is not None
+    if has_v:
+        _check_tensor(values, "values", bits, n)
+    keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+    _check_tensor(keys_out, "keys_out", bits, n)
+    if has_v:
+        values_out = torch.empty_like(values) if values_out is None else values_out
+        _check_tensor(values_out, "values_out", bits, n)
+    else:
+        values_out = None
+    ctx = ctx or context(keys.device.index)
+    if n:
+        flags = _order_flags(keys, order, descending)
+        ws = workspace if workspace is not None else _workspace(
+            ctx, ctx.merge_workspace_bytes(bits, has_v, n), keys.device)
+        kt = RS_KEY_U32 if bits == 32 else RS_KEY_U64
+        _check(lib().rs_merge_sort(ctx.handle, kt, flags, _ptr(keys), _ptr(values),
+                                   _ptr(keys_out), _ptr(values_out), n, _ptr(ws), ws.numel(),
+                                   _stream(ctx.device)))
+    return (keys_out, values_out) if has_v else keys_out

@@ -11,9 +11,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "librs.so")
 # rs_sort.hip: host logic and the configuration-independent kernels; the
-# rs_var_* units instantiate the digit-pass kernels of every configuration.
+# rs_var_* units instantiate the digit-pass kernels of every configuration;
+# rs_merge.hip holds the merge sort's kernels.
 SOURCES = ["rs_sort.hip", "rs_var_u32.hip", "rs_var_u64.hip", "rs_var_u32_seg.hip",
-           "rs_var_u64_seg.hip"]
+           "rs_var_u64_seg.hip", "rs_merge.hip"]
 OBJ_DIR = os.path.join(PKG, "_build")
 
 HIPCC_FLAGS = [

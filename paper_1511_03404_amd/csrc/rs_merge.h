@@ -1,0 +1,371 @@
+// Stable merge sort (paper, Section 2.4: cut the sequence into runs, sort
+// each, merge sorted runs with a stable merge until one remains), the
+// comparison-based counterpart of the radix path.
+//
+//   k_merge_tile   one workgroup sorts a tile of THREADS x ITEMS elements:
+//                  each thread sorts its ITEMS in registers with an odd-even
+//                  transposition network, then the workgroup merges runs of
+//                  ITEMS, 2 ITEMS, ... in LDS until the tile is one run;
+//   k_merge_split  for one merge level (runs of w elements merged pairwise),
+//                  the merge-path split of every output tile: how many of the
+//                  tile's first outputs come from the left run;
+//   k_merge_pass   one workgroup per output tile: stage the tile's share of
+//                  both runs in LDS, each thread merges ITEMS outputs from its
+//                  own split, then a coalesced store.
+//
+// Every merge is stable: on equal keys the left run's element goes first,
+// and in a split the left run gives every element <= the right run's next.
+// Keys are compared after the key-order map (applied on the tile sort's
+// load, undone on the last store).  Positions are 32-bit (n < 2^30).
+#pragma once
+
+#include "rs_device.h"
+
+namespace rs {
+
+// Tile shapes: the tile sort fills a CU's LDS (8192 elements), the merge
+// pass keeps two workgroups per CU.
+template <typename K, bool HAS_V>
+struct MergeShape {
+    static constexpr int kTileThreads = 512;
+    static constexpr int kPassThreads = 256;
+    static constexpr int kItems = 16;
+    static constexpr int kTile = kTileThreads * kItems;      // elements per tile sort
+    static constexpr int kPassTile = kPassThreads * kItems;  // outputs per merge-pass tile
+};
+
+// LDS slot of element e: one element of padding after every ITEMS, so that
+// the lanes of a wave reading their own ITEMS consecutive elements hit
+// different banks (lane stride ITEMS + 1 elements).
+template <int ITEMS>
+__device__ __forceinline__ uint32_t lds_slot(uint32_t e)
+{
+    return e + e / ITEMS;
+}
+
+template <int N, int ITEMS>
+struct PaddedLen {
+    static constexpr int value = N + N / ITEMS;
+};
+
+// Merge-path split of a stable merge of A[0, na) and B[0, nb): the number i
+// of A elements among the first `diag` outputs.  Every A[x], x < i, precedes
+// B[diag - i] (A[x] <= B), every B[y], y < diag - i, precedes A[i] (B < A).
+template <typename K, typename GetA, typename GetB>
+__device__ __forceinline__ uint32_t merge_split(uint32_t diag, uint32_t na, uint32_t nb, GetA A,
+                                                GetB B)
+{
+    uint32_t lo = diag > nb ? diag - nb : 0u;
+    uint32_t hi = diag < na ? diag : na;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A(mid) <= B(diag - 1 - mid))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Serial stable merge of ITEMS outputs from LDS runs [ia, ea) and [ib, eb)
+// (LDS element positions, unpadded): keys into key[], source positions into
+// src[] (the values follow them afterwards).
+template <typename K, int ITEMS, int PAD_ITEMS>
+__device__ __forceinline__ void merge_serial(const K *s_k, uint32_t ia, uint32_t ea, uint32_t ib,
+                                             uint32_t eb, K (&key)[ITEMS],
+                                             uint32_t (&src)[ITEMS])
+{
+    K a = ia < ea ? s_k[lds_slot<PAD_ITEMS>(ia)] : (K)0;
+    K b = ib < eb ? s_k[lds_slot<PAD_ITEMS>(ib)] : (K)0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool take_a = ib >= eb || (ia < ea && a <= b);
+        key[j] = take_a ? a : b;
+        src[j] = take_a ? ia : ib;
+        ia += take_a;
+        ib += !take_a;
+        const uint32_t nx = take_a ? ia : ib;
+        const bool more = take_a ? ia < ea : ib < eb;
+        const K nk = more ? s_k[lds_slot<PAD_ITEMS>(nx)] : (K)0;
+        a = take_a ? nk : a;
+        b = take_a ? b : nk;
+    }
+}
+
+// Stable odd-even transposition sort of ITEMS registers: ITEMS rounds of
+// compare-exchanges between neighbours, exchanging only strictly greater
+// keys, so equal keys never pass each other.
+template <typename K, typename V, bool HAS_V, int ITEMS>
+__device__ __forceinline__ void register_sort(K (&key)[ITEMS], V (&val)[HAS_V ? ITEMS : 1])
+{
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+#pragma unroll
+        for (int j = r & 1; j + 1 < ITEMS; j += 2) {
+            const bool sw = key[j] > key[j + 1];
+            const K lo = sw ? key[j + 1] : key[j];
+            const K hi = sw ? key[j] : key[j + 1];
+            key[j] = lo;
+            key[j + 1] = hi;
+            if constexpr (HAS_V) {
+                const V vl = sw ? val[j + 1] : val[j];
+                const V vh = sw ? val[j] : val[j + 1];
+                val[j] = vl;
+                val[j + 1] = vh;
+            }
+        }
+    }
+}
+
+struct MergeTileArgs {
+    const void *kin;
+    const void *vin;
+    void *kout;
+    void *vout;
+    uint32_t n;
+    uint32_t map_load;   // key order applied on load
+    uint32_t map_store;  // key order undone on store (when no merge level follows)
+};
+
+template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_merge_tile(MergeTileArgs a)
+{
+    constexpr uint32_t T = THREADS * ITEMS;
+    constexpr int SLOTS = PaddedLen<T, ITEMS>::value;
+    __shared__ K s_k[SLOTS];
+    __shared__ V s_v[HAS_V ? SLOTS : 1];
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = blockIdx.x * T;
+    const uint32_t valid = min(T, a.n - base);
+    const K *kin = (const K *)a.kin + base;
+    const V *vin = HAS_V ? (const V *)a.vin + base : nullptr;
+
+    // coalesced load into LDS; padding keys (all ones) stay behind every
+    // real key because they come last and every merge is stable
+    {
+        K key[ITEMS];
+        V val[HAS_V ? ITEMS : 1];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = j * THREADS + t;
+            key[j] = e < valid ? kin[e] : KeyTraits<K>::kPad;
+            if constexpr (HAS_V)
+                val[j] = e < valid ? vin[e] : (V)0;
+        }
+        if (a.map_load) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) {
+                const K mk = map_in(key[j], a.map_load);
+                key[j] = j * THREADS + t < valid ? mk : key[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t e = j * THREADS + t;
+            s_k[lds_slot<ITEMS>(e)] = key[j];
+            if constexpr (HAS_V)
+                s_v[lds_slot<ITEMS>(e)] = val[j];
+        }
+    }
+    __syncthreads();
+
+    // each thread: its ITEMS consecutive elements, sorted in registers
+    K key[ITEMS];
+    V val[HAS_V ? ITEMS : 1];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        key[j] = s_k[lds_slot<ITEMS>(t * ITEMS + j)];
+        if constexpr (HAS_V)
+            val[j] = s_v[lds_slot<ITEMS>(t * ITEMS + j)];
+    }
+    register_sort<K, V, HAS_V, ITEMS>(key, val);
+
+    // merge runs of w elements pairwise in LDS, w = ITEMS, 2 ITEMS, ...
+    for (uint32_t w = ITEMS; w < T; w *= 2) {
+        __syncthreads();  // every read of the previous round is done
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            s_k[lds_slot<ITEMS>(t * ITEMS + j)] = key[j];
+            if constexpr (HAS_V)
+                s_v[lds_slot<ITEMS>(t * ITEMS + j)] = val[j];
+        }
+        __syncthreads();
+        const uint32_t o = t * ITEMS;          // first output of this thread
+        const uint32_t pb = o & ~(2 * w - 1);  // its pair of runs
+        const uint32_t diag = o - pb;
+        const uint32_t i = merge_split<K>(
+            diag, w, w, [&](uint32_t x) { return s_k[lds_slot<ITEMS>(pb + x)]; },
+            [&](uint32_t y) { return s_k[lds_slot<ITEMS>(pb + w + y)]; });
+        uint32_t src[ITEMS];
+        merge_serial<K, ITEMS, ITEMS>(s_k, pb + i, pb + w, pb + w + (diag - i), pb + 2 * w, key,
+                                      src);
+        if constexpr (HAS_V) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j)
+                val[j] = s_v[lds_slot<ITEMS>(src[j])];
+        }
+    }
+
+    // blocked registers -> LDS -> coalesced store
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        s_k[lds_slot<ITEMS>(t * ITEMS + j)] = key[j];
+        if constexpr (HAS_V)
+            s_v[lds_slot<ITEMS>(t * ITEMS + j)] = val[j];
+    }
+    __syncthreads();
+    K *kout = (K *)a.kout + base;
+    V *vout = HAS_V ? (V *)a.vout + base : nullptr;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * THREADS + t;
+        if (e < valid) {
+            kout[e] = map_out(s_k[lds_slot<ITEMS>(e)], a.map_store);
+            if constexpr (HAS_V)
+                vout[e] = s_v[lds_slot<ITEMS>(e)];
+        }
+    }
+}
+
+// One merge level: runs [q 2w, q 2w + w) and [q 2w + w, q 2w + 2w) (clipped
+// to n) merge into [q 2w, q 2w + 2w).
+struct MergeLevelArgs {
+    const void *sk;
+    const void *sv;
+    void *dk;
+    void *dv;
+    uint32_t *split;  // per output-tile boundary: absolute position in the left run
+    uint32_t n;
+    uint32_t w;          // run length of this level
+    uint32_t tiles;      // output tiles of the merge pass
+    uint32_t map_store;  // key order undone on store (last level only)
+};
+
+// Pair of runs holding output position g, and the lengths of its two runs.
+struct PairRuns {
+    uint32_t base, na, nb;
+};
+
+__device__ __forceinline__ PairRuns pair_runs(uint32_t g, uint32_t w, uint32_t n)
+{
+    PairRuns p;
+    p.base = g / (2 * w) * (2 * w);
+    const uint32_t left = n - p.base;
+    p.na = min(w, left);
+    p.nb = left > w ? min(w, left - w) : 0u;
+    return p;
+}
+
+template <typename K, int TILE>
+__global__ __launch_bounds__(256) void k_merge_split(MergeLevelArgs a)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= a.tiles)
+        return;
+    // the split at the start of output tile b (tiles never straddle a pair:
+    // TILE divides 2w)
+    const uint32_t g = b * TILE;
+    const PairRuns p = pair_runs(g, a.w, a.n);
+    const K *A = (const K *)a.sk + p.base;
+    const K *B = A + a.w;
+    const uint32_t i = merge_split<K>(
+        g - p.base, p.na, p.nb, [&](uint32_t x) { return A[x]; },
+        [&](uint32_t y) { return B[y]; });
+    a.split[b] = p.base + i;
+}
+
+template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_merge_pass(MergeLevelArgs a)
+{
+    constexpr uint32_t T = THREADS * ITEMS;
+    constexpr int SLOTS = PaddedLen<T, ITEMS>::value;
+    __shared__ K s_k[SLOTS];
+    __shared__ V s_v[HAS_V ? SLOTS : 1];
+
+    const uint32_t t = threadIdx.x;
+    const uint32_t b = blockIdx.x;
+    const uint32_t g0 = b * T;
+    const uint32_t g1 = min(g0 + T, a.n);
+    const PairRuns p = pair_runs(g0, a.w, a.n);
+    const uint32_t a_begin = p.base, b_begin = p.base + a.w;
+    // this tile's share of each run
+    const uint32_t a0 = a.split[b];
+    const uint32_t b0 = b_begin + (g0 - p.base) - (a0 - a_begin);
+    uint32_t a1, b1;
+    if (g1 == p.base + p.na + p.nb) {  // the tile ends its pair
+        a1 = a_begin + p.na;
+        b1 = b_begin + p.nb;
+    } else {
+        a1 = a.split[b + 1];
+        b1 = b_begin + (g1 - p.base) - (a1 - a_begin);
+    }
+    const uint32_t ca = a1 - a0, cb = b1 - b0;  // ca + cb = g1 - g0
+
+    const K *sk = (const K *)a.sk;
+    const V *sv = HAS_V ? (const V *)a.sv : nullptr;
+    // stage A's share at [0, ca) and B's at [ca, ca + cb), coalesced
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * THREADS + t;
+        if (e < ca + cb) {
+            const uint32_t s = e < ca ? a0 + e : b0 + (e - ca);
+            s_k[lds_slot<ITEMS>(e)] = sk[s];
+            if constexpr (HAS_V)
+                s_v[lds_slot<ITEMS>(e)] = sv[s];
+        }
+    }
+    __syncthreads();
+
+    const uint32_t o = t * ITEMS;
+    K key[ITEMS];
+    V val[HAS_V ? ITEMS : 1];
+    uint32_t src[ITEMS];
+    {
+        const uint32_t d = min(o, ca + cb);
+        const uint32_t i = merge_split<K>(
+            d, ca, cb, [&](uint32_t x) { return s_k[lds_slot<ITEMS>(x)]; },
+            [&](uint32_t y) { return s_k[lds_slot<ITEMS>(ca + y)]; });
+        merge_serial<K, ITEMS, ITEMS>(s_k, i, ca, ca + (d - i), ca + cb, key, src);
+    }
+    if constexpr (HAS_V) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            val[j] = o + j < ca + cb ? s_v[lds_slot<ITEMS>(src[j])] : (V)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (o + j < ca + cb) {
+            s_k[lds_slot<ITEMS>(o + j)] = key[j];
+            if constexpr (HAS_V)
+                s_v[lds_slot<ITEMS>(o + j)] = val[j];
+        }
+    }
+    __syncthreads();
+    K *dk = (K *)a.dk + g0;
+    V *dv = HAS_V ? (V *)a.dv + g0 : nullptr;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t e = j * THREADS + t;
+        if (e < ca + cb) {
+            dk[e] = map_out(s_k[lds_slot<ITEMS>(e)], a.map_store);
+            if constexpr (HAS_V)
+                dv[e] = s_v[lds_slot<ITEMS>(e)];
+        }
+    }
+}
+
+// Host-side table of the merge sort's kernels for one kind.
+struct MergeOps {
+    int tile;       // elements per tile sort
+    int pass_tile;  // outputs per merge-pass workgroup
+    void (*tile_sort)(const MergeTileArgs &, uint32_t grid, hipStream_t);
+    void (*split)(const MergeLevelArgs &, uint32_t grid, hipStream_t);
+    void (*pass)(const MergeLevelArgs &, uint32_t grid, hipStream_t);
+};
+
+const MergeOps &merge_ops(int key_bytes, bool has_values);
+
+}  // namespace rs

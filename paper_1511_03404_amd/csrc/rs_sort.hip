@@ -27,6 +27,7 @@
 #include "rs_block.h"
 #include "rs_configs.h"
 #include "rs_device.h"
+#include "rs_merge.h"
 #include "rs_ops.h"
 #include "rs_segmented.h"
 
@@ -308,17 +309,10 @@ static rs_status get_workspace(rs_context *ctx, void *ws, size_t ws_bytes, uint6
     return RS_OK;
 }
 
-static rs_status validate_sort(const rs_context *ctx, int key_bytes, const void *kin,
-                               const void *vin, void *kout, void *vout, bool has_values,
-                               uint64_t n, const void *ws, size_t ws_bytes, const SortOps &op,
-                               Layout *L)
+// Pointer checks shared by every sort (n > 0).
+static rs_status validate_data(int key_bytes, const void *kin, const void *vin, void *kout,
+                               void *vout, bool has_values, uint64_t n)
 {
-    if (n >= RS_MAX_ELEMENTS)
-        return fail(RS_ERR_UNSUPPORTED, "n = %llu exceeds the limit of 2^30 - 1 elements",
-                    (unsigned long long)n);
-    *L = make_layout(key_bytes, has_values, n, op);
-    if (n == 0)
-        return RS_OK;
     if (!kin || !kout || (has_values && (!vin || !vout)))
         return fail(RS_ERR_INVALID_ARGUMENT, "NULL data pointer with n > 0");
     const uintptr_t al = (uintptr_t)key_bytes - 1;
@@ -335,17 +329,44 @@ static rs_status validate_sort(const rs_context *ctx, int key_bytes, const void 
             overlaps(kout, bytes, vin, bytes) || overlaps(kout, bytes, vout, bytes))
             return fail(RS_ERR_INVALID_ARGUMENT, "key and value arrays overlap");
     }
-    if (ws) {
-        if ((uintptr_t)ws & 255)
-            return fail(RS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
-        if (ws_bytes < L->total)
-            return fail(RS_ERR_INVALID_ARGUMENT, "workspace of %zu bytes is below the %llu needed",
-                        ws_bytes, (unsigned long long)L->total);
-        if (overlaps(ws, L->total, kin, bytes) || overlaps(ws, L->total, kout, bytes) ||
-            (has_values && (overlaps(ws, L->total, vin, bytes) || overlaps(ws, L->total, vout, bytes))))
-            return fail(RS_ERR_INVALID_ARGUMENT, "workspace overlaps a data array");
-    }
     return RS_OK;
+}
+
+// Checks of a caller's workspace of `need` bytes (none given: the context's own).
+static rs_status validate_ws(int key_bytes, const void *kin, const void *vin, const void *kout,
+                             const void *vout, bool has_values, uint64_t n, const void *ws,
+                             size_t ws_bytes, uint64_t need)
+{
+    if (!ws)
+        return RS_OK;
+    const uint64_t bytes = n * (uint64_t)key_bytes;
+    if ((uintptr_t)ws & 255)
+        return fail(RS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(RS_ERR_INVALID_ARGUMENT, "workspace of %zu bytes is below the %llu needed",
+                    ws_bytes, (unsigned long long)need);
+    if (overlaps(ws, need, kin, bytes) || overlaps(ws, need, kout, bytes) ||
+        (has_values && (overlaps(ws, need, vin, bytes) || overlaps(ws, need, vout, bytes))))
+        return fail(RS_ERR_INVALID_ARGUMENT, "workspace overlaps a data array");
+    return RS_OK;
+}
+
+static rs_status validate_sort(const rs_context *ctx, int key_bytes, const void *kin,
+                               const void *vin, void *kout, void *vout, bool has_values,
+                               uint64_t n, const void *ws, size_t ws_bytes, const SortOps &op,
+                               Layout *L)
+{
+    (void)ctx;
+    if (n >= RS_MAX_ELEMENTS)
+        return fail(RS_ERR_UNSUPPORTED, "n = %llu exceeds the limit of 2^30 - 1 elements",
+                    (unsigned long long)n);
+    *L = make_layout(key_bytes, has_values, n, op);
+    if (n == 0)
+        return RS_OK;
+    rs_status st = validate_data(key_bytes, kin, vin, kout, vout, has_values, n);
+    if (st != RS_OK)
+        return st;
+    return validate_ws(key_bytes, kin, vin, kout, vout, has_values, n, ws, ws_bytes, L->total);
 }
 
 template <typename K, bool HAS_V>
@@ -459,6 +480,107 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         });
     }
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(RS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return RS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Merge sort host side: one tile-sort launch, then per merge level a split
+// launch and a merge-pass launch, ping-ponging between the output and the
+// scratch copy so that the last level writes the output.
+
+struct MergeLayout {
+    uint64_t tiles;       // tile sorts
+    uint64_t pass_tiles;  // merge-pass workgroups per level
+    int levels;           // merge levels: runs double from the tile size until >= n
+    uint64_t off_split, off_tmp_k, off_tmp_v, total;
+};
+
+static MergeLayout make_merge_layout(int key_bytes, bool has_values, uint64_t n,
+                                     const MergeOps &op)
+{
+    MergeLayout L{};
+    L.tiles = (n + op.tile - 1) / op.tile;
+    L.pass_tiles = (n + op.pass_tile - 1) / op.pass_tile;
+    for (uint64_t w = op.tile; w < n; w *= 2)
+        ++L.levels;
+    uint64_t o = 0;
+    L.off_split = o;
+    o = align_up(o + (L.pass_tiles + 1) * 4, 256);
+    L.off_tmp_k = o;
+    o = align_up(o + n * key_bytes, 256);
+    L.off_tmp_v = o;
+    o = align_up(o + (has_values ? n * key_bytes : 0), 256);
+    L.total = o;
+    return L;
+}
+
+template <typename K, bool HAS_V>
+static const char *merge_pass_name()
+{
+    if (sizeof(K) == 4)
+        return HAS_V ? "k_merge_pass_u32_pairs" : "k_merge_pass_u32_keys";
+    return HAS_V ? "k_merge_pass_u64_pairs" : "k_merge_pass_u64_keys";
+}
+
+template <typename K, bool HAS_V>
+static rs_status run_merge(rs_context *ctx, const K *kin, const K *vin, K *kout, K *vout,
+                           uint64_t n, void *ws, size_t ws_bytes, void *stream, uint32_t kmap)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (n >= RS_MAX_ELEMENTS)
+        return fail(RS_ERR_UNSUPPORTED, "n = %llu exceeds the limit of 2^30 - 1 elements",
+                    (unsigned long long)n);
+    if (n == 0)
+        return RS_OK;
+    const MergeOps &op = merge_ops(sizeof(K), HAS_V);
+    const MergeLayout L = make_merge_layout(sizeof(K), HAS_V, n, op);
+    rs_status st = validate_data(sizeof(K), kin, vin, kout, vout, HAS_V, n);
+    if (st != RS_OK)
+        return st;
+    st = validate_ws(sizeof(K), kin, vin, kout, vout, HAS_V, n, ws, ws_bytes, L.total);
+    if (st != RS_OK)
+        return st;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    char *wb = nullptr;
+    if (L.levels > 0) {
+        void *w = nullptr;
+        st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
+        if (st != RS_OK)
+            return st;
+        wb = (char *)w;
+    }
+    // buffers: 0 = output, 1 = scratch; the tile sort writes the one from
+    // which an even or odd number of levels ends in the output
+    K *bk[2] = {kout, wb ? (K *)(wb + L.off_tmp_k) : nullptr};
+    K *bv[2] = {vout, (wb && HAS_V) ? (K *)(wb + L.off_tmp_v) : nullptr};
+    int cur = L.levels & 1;
+    MergeTileArgs ta{kin, vin, bk[cur], bv[cur], (uint32_t)n, kmap, L.levels == 0 ? kmap : 0u};
+    launch(ctx, s, "k_merge_tile", [&] { op.tile_sort(ta, (uint32_t)L.tiles, s); });
+    uint32_t *split = wb ? (uint32_t *)(wb + L.off_split) : nullptr;
+    for (int lvl = 0; lvl < L.levels; ++lvl) {
+        MergeLevelArgs la{};
+        la.sk = bk[cur];
+        la.sv = bv[cur];
+        la.dk = bk[cur ^ 1];
+        la.dv = bv[cur ^ 1];
+        la.split = split;
+        la.n = (uint32_t)n;
+        la.w = (uint32_t)op.tile << lvl;
+        la.tiles = (uint32_t)L.pass_tiles;
+        la.map_store = lvl == L.levels - 1 ? kmap : 0u;
+        launch(ctx, s, "k_merge_split",
+               [&] { op.split(la, (uint32_t)((L.pass_tiles + 255) / 256), s); });
+        launch(ctx, s, merge_pass_name<K, HAS_V>(),
+               [&] { op.pass(la, (uint32_t)L.pass_tiles, s); });
+        cur ^= 1;
+    }
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(RS_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return RS_OK;
@@ -918,6 +1040,49 @@ rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *k
                                               num_segments, total, ws, ws_bytes, stream);
     }
     return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+}
+
+rs_status rs_merge_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int has_values,
+                                   uint64_t n, size_t *bytes)
+{
+    if (!ctx || !bytes)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx or bytes is NULL");
+    if (key_type != RS_KEY_U32 && key_type != RS_KEY_U64)
+        return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+    if (n >= RS_MAX_ELEMENTS)
+        return fail(RS_ERR_UNSUPPORTED, "n = %llu exceeds the limit of 2^30 - 1 elements",
+                    (unsigned long long)n);
+    const int kb = key_type == RS_KEY_U32 ? 4 : 8;
+    *bytes = (size_t)make_merge_layout(kb, has_values != 0, n, merge_ops(kb, has_values != 0))
+                 .total;
+    return RS_OK;
+}
+
+rs_status rs_merge_sort(rs_context *ctx, rs_key_type key_type, uint32_t order,
+                        const void *keys_in, const void *vals_in, void *keys_out, void *vals_out,
+                        uint64_t n, void *ws, size_t ws_bytes, void *stream)
+{
+    rs_status st;
+    const uint32_t kmap = order_map(key_type, order, &st);
+    if (st != RS_OK)
+        return st;
+    if ((vals_in != nullptr) != (vals_out != nullptr))
+        return fail(RS_ERR_INVALID_ARGUMENT, "vals_in and vals_out must both be given or both NULL");
+    if (key_type == RS_KEY_U32) {
+        if (vals_in)
+            return run_merge<uint32_t, true>(ctx, (const uint32_t *)keys_in,
+                                             (const uint32_t *)vals_in, (uint32_t *)keys_out,
+                                             (uint32_t *)vals_out, n, ws, ws_bytes, stream, kmap);
+        return run_merge<uint32_t, false>(ctx, (const uint32_t *)keys_in, nullptr,
+                                          (uint32_t *)keys_out, nullptr, n, ws, ws_bytes, stream,
+                                          kmap);
+    }
+    if (vals_in)
+        return run_merge<uint64_t, true>(ctx, (const uint64_t *)keys_in, (const uint64_t *)vals_in,
+                                         (uint64_t *)keys_out, (uint64_t *)vals_out, n, ws,
+                                         ws_bytes, stream, kmap);
+    return run_merge<uint64_t, false>(ctx, (const uint64_t *)keys_in, nullptr,
+                                      (uint64_t *)keys_out, nullptr, n, ws, ws_bytes, stream, kmap);
 }
 
 rs_status rs_config_count(rs_key_type key_type, int has_values, int *count)

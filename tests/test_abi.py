@@ -217,3 +217,29 @@ def test_order_flag_errors(rs, ctx):
     assert rs._order_flags(torch.empty(4, dtype=torch.float32), None, True) \
         == rs.RS_ORDER_FLOAT | rs.RS_ORDER_DESCENDING
     assert rs._order_flags(torch.empty(4, dtype=torch.int64), None, False) == 0
+
+
+def test_merge_sort_argument_errors(rs, ctx):
+    """rs_merge_sort validates on the host like rs_sort."""
+    L = rs.lib()
+    fake = 0x7F0000000000
+    assert L.rs_merge_sort(ctx.handle, 0, 0, None, None, None, None, 0, None, 0, None) == rs.RS_OK
+    assert L.rs_merge_sort(ctx.handle, 0, 0, None, None, fake, None, 10, None, 0, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_merge_sort(ctx.handle, 0, 3, fake, None, fake + 8192, None, 10, None, 0, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_merge_sort(ctx.handle, 0, 0, fake, fake + 8192, fake + 16384, None, 10, None, 0,
+                           None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_merge_sort(ctx.handle, 0, 0, fake, None, fake + 16, None, 100, None, 0, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"overlap" in L.rs_last_error()
+    assert L.rs_merge_sort(ctx.handle, 0, 0, fake, None, fake + (1 << 33), None, 1 << 30, None,
+                           0, None) == rs.RS_ERR_UNSUPPORTED
+    need = ctx.merge_workspace_bytes(32, True, 100000)
+    assert need >= 100000 * 8
+    assert ctx.merge_workspace_bytes(64, False, 8192) > 0
+    ws = fake + (1 << 34)
+    assert L.rs_merge_sort(ctx.handle, 0, 0, fake, fake + (1 << 20), fake + (1 << 21),
+                           fake + (1 << 22), 100000, ws, need - 1, None) \
+        == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"workspace" in L.rs_last_error()
