@@ -41,6 +41,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources are stale
 KERNEL_SOURCES = ("paper_1511_03404_amd/csrc/rs_kernels.h", "paper_1511_03404_amd/csrc/rs_device.h",
                   "paper_1511_03404_amd/csrc/rs_segmented.h")
+MERGE_SOURCES = ("paper_1511_03404_amd/csrc/rs_merge.h", "paper_1511_03404_amd/csrc/rs_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -51,24 +52,29 @@ def pass_kernel_name(bits, has_v, cfg):
             f"rs::PassCfg<{cfg['radix_bits']}, {cfg['threads']}, {cfg['items']}> >")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, cfg):
-    """HBM bytes per digit-pass launch from the committed counter summary,
-    or None if it is missing, was taken on a different kernel source or on
-    another configuration."""
+    """HBM bytes per launch of the workload's dominant kernel from the
+    committed counter summary, or None if it is missing, was taken on a
+    different kernel source or on another configuration."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
+    if workload.startswith("merge_"):
+        w = t.get("merge", {}).get(workload)
+        if w is None or w.get("source_sha256_16") != kernel_source_hash(MERGE_SOURCES):
+            return None
+        return w.get("traffic_bytes_per_launch")
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     w = t.get("workloads", {}).get(workload)
@@ -115,6 +121,22 @@ def summarize_pmc(root):
                                "write_kib_per_launch": round(wr, 1),
                                "traffic_bytes_per_launch": int(f * 1024 * fs + wr * 1024 * ws),
                                "launches_sampled": nf}
+    # the merge pass, per merge kind measured (bench.py --workload merge)
+    for w, (_, bits, has_v, _) in WORKLOADS.items():
+        t = "unsigned int" if bits == 32 else "unsigned long"
+        k = (f"void rs::k_merge_pass<{t}, {t}, {'true' if has_v else 'false'}, "
+             f"{'512, 4' if bits == 64 else '256, 8'}, 1>")
+        fp = os.path.join(root, "merge_" + w, "FETCH_SIZE", "run_counter_collection.csv")
+        wp = os.path.join(root, "merge_" + w, "WRITE_SIZE", "run_counter_collection.csv")
+        if not (os.path.exists(fp) and os.path.exists(wp)):
+            continue
+        f, nf = mean(fp, k)
+        wr, _ = mean(wp, k)
+        out.setdefault("merge", {})["merge_" + w] = {
+            "kernel": k, "source_sha256_16": kernel_source_hash(MERGE_SOURCES),
+            "fetch_kib_per_launch": round(f, 1), "write_kib_per_launch": round(wr, 1),
+            "traffic_bytes_per_launch": int(f * 1024 * fs + wr * 1024 * ws),
+            "launches_sampled": nf}
     return out
 
 
@@ -508,12 +530,15 @@ def bench_merge(args, torch, rs, datagen, dev):
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "kernel": pass_name,
                     "kernel_instance": f"void rs::k_merge_pass<{t}, {t}, "
-                                       f"{'true' if has_v else 'false'}, 256, 16>",
+                                       f"{'true' if has_v else 'false'}, "
+                                       f"{'512, 4' if bits == 64 else '256, 8'}, 1>",
                     "avg_launch_ms": round(avg, 5), "launches": len(pass_ms),
                     "bytes_per_launch": bytes_per_launch, "input": dists[ref]}
     levels = 0
     while (8192 << levels) < n:
         levels += 1
+    if roofline is not None:
+        roofline["traffic"] = measured_traffic("merge_" + args.merge_kind, None)
     out = {
         "metric": "Mkeys/s (stable merge sort)", "value": round(n * len(dists) * args.steps /
                                                                  elapsed / 1e6, 1),
@@ -522,13 +547,13 @@ def bench_merge(args, torch, rs, datagen, dev):
         "scaling": "weak", "vs_baseline": None, "dtype": f"u{bits}", "data": "synthetic",
         "config": {"workload": f"merge sort of {wdesc}; one sort per distribution per step "
                                f"({', '.join(dists)}); MT19937 seed 1; tiles of 8192 sorted "
-                               f"in LDS, then {levels} merge levels",
+                               f"in LDS, then {levels} merge levels of 2048-output workgroups",
                    "n": n, "key_bits": bits, "value_bits": bits if has_v else 0,
                    "distributions": dists, "merge_levels": levels},
         "roofline": roofline, "per_distribution": per,
     }
     if not args.no_cpu_baseline:
-        m = 1 << min(args.cpu_sample_log2, n.bit_length() - 1, 24)
+        m = 1 << min(args.cpu_sample_log2, n.bit_length() - 1, 25)
         tot = 0.0
         for d in dists:
             k = datagen.keys(d, m, bits, seed=1)

@@ -210,7 +210,7 @@ rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_
  * write every element once.  keys_in may equal keys_out (and vals_in
  * vals_out): in place.  ws: a device buffer of at least
  * rs_merge_workspace_bytes() bytes (scratch copies of keys and values and
- * one split word per 4096 outputs), 256-byte aligned, or NULL for the
+ * one split word per 2048 outputs), 256-byte aligned, or NULL for the
  * context's own; n <= 8192 needs none.  Errors as rs_sort.
  */
 rs_status rs_merge_sort(rs_context *ctx, rs_key_type key_type, uint32_t order,

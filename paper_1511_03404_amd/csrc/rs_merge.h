@@ -11,7 +11,7 @@
 //                  tile's first outputs come from the left run;
 //   k_merge_pass   one workgroup per output tile: stage the tile's share of
 //                  both runs in LDS, each thread merges ITEMS outputs from its
-//                  own split, then a coalesced store.
+//                  own splits, then a coalesced store.
 //
 // Every merge is stable: on equal keys the left run's element goes first,
 // and in a split the left run gives every element <= the right run's next.
@@ -23,15 +23,21 @@
 
 namespace rs {
 
-// Tile shapes: the tile sort fills a CU's LDS (8192 elements), the merge
-// pass keeps two workgroups per CU.
+// Shapes measured on MI355X (2^26 32-bit and 2^25 64-bit pairs): short
+// per-thread merges and many waves hide the LDS latency of the merge better
+// than long ones; more than one merge chain per thread (interleaved chains,
+// each with its own split) costs more ALU than it hides.  Tile sorts of 8192
+// elements; merge-pass workgroups of 2048 outputs.
 template <typename K, bool HAS_V>
 struct MergeShape {
-    static constexpr int kTileThreads = 512;
-    static constexpr int kPassThreads = 256;
-    static constexpr int kItems = 16;
-    static constexpr int kTile = kTileThreads * kItems;      // elements per tile sort
-    static constexpr int kPassTile = kPassThreads * kItems;  // outputs per merge-pass tile
+    static constexpr int kTileThreads = 1024;
+    static constexpr int kTileItems = 8;
+    static constexpr int kTileChains = 1;  // independent merge chains per thread
+    static constexpr int kPassThreads = sizeof(K) == 8 ? 512 : 256;
+    static constexpr int kPassItems = sizeof(K) == 8 ? 4 : 8;
+    static constexpr int kPassChains = 1;
+    static constexpr int kTile = kTileThreads * kTileItems;      // elements per tile sort
+    static constexpr int kPassTile = kPassThreads * kPassItems;  // outputs per merge-pass tile
 };
 
 // LDS slot of element e: one element of padding after every ITEMS, so that
@@ -48,47 +54,76 @@ struct PaddedLen {
     static constexpr int value = N + N / ITEMS;
 };
 
-// Merge-path split of a stable merge of A[0, na) and B[0, nb): the number i
-// of A elements among the first `diag` outputs.  Every A[x], x < i, precedes
-// B[diag - i] (A[x] <= B), every B[y], y < diag - i, precedes A[i] (B < A).
-template <typename K, typename GetA, typename GetB>
-__device__ __forceinline__ uint32_t merge_split(uint32_t diag, uint32_t na, uint32_t nb, GetA A,
-                                                GetB B)
-{
-    uint32_t lo = diag > nb ? diag - nb : 0u;
-    uint32_t hi = diag < na ? diag : na;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (A(mid) <= B(diag - 1 - mid))
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// Serial stable merge of ITEMS outputs from LDS runs [ia, ea) and [ib, eb)
-// (LDS element positions, unpadded): keys into key[], source positions into
-// src[] (the values follow them afterwards).
-template <typename K, int ITEMS, int PAD_ITEMS>
-__device__ __forceinline__ void merge_serial(const K *s_k, uint32_t ia, uint32_t ea, uint32_t ib,
-                                             uint32_t eb, K (&key)[ITEMS],
+// ITEMS outputs of one thread as C interleaved chains of ITEMS / C outputs,
+// each from its own merge-path split: the LDS reads of different chains are
+// independent, so C of them are in flight where one chain would wait for
+// each.  Runs are [0, na) and [na, na + nb) of the LDS positions starting
+// at `base`; the thread's first output is `diag` (<= na + nb).
+//
+// The merge-path split of output d is the number i of left-run elements
+// among the first d outputs of the stable merge: every A[x], x < i,
+// precedes B[d - i] (A[x] <= B[d - i]) and every B[y], y < d - i, precedes
+// A[i] (B[y] < A[i]); a binary search finds it.  From there the merge takes
+// the left element whenever it is <= the right one.
+template <typename K, int ITEMS, int C, int PAD_ITEMS>
+__device__ __forceinline__ void merge_chains(const K *s_k, uint32_t base, uint32_t na, uint32_t nb,
+                                             uint32_t diag, K (&key)[ITEMS],
                                              uint32_t (&src)[ITEMS])
 {
-    K a = ia < ea ? s_k[lds_slot<PAD_ITEMS>(ia)] : (K)0;
-    K b = ib < eb ? s_k[lds_slot<PAD_ITEMS>(ib)] : (K)0;
+    constexpr int L = ITEMS / C;
+    static_assert(L * C == ITEMS, "chains split the items evenly");
+    const uint32_t total = na + nb;
+    uint32_t d[C], lo[C], hi[C];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const bool take_a = ib >= eb || (ia < ea && a <= b);
-        key[j] = take_a ? a : b;
-        src[j] = take_a ? ia : ib;
-        ia += take_a;
-        ib += !take_a;
-        const uint32_t nx = take_a ? ia : ib;
-        const bool more = take_a ? ia < ea : ib < eb;
-        const K nk = more ? s_k[lds_slot<PAD_ITEMS>(nx)] : (K)0;
-        a = take_a ? nk : a;
-        b = take_a ? b : nk;
+    for (int c = 0; c < C; ++c) {
+        d[c] = min(diag + c * L, total);
+        lo[c] = d[c] > nb ? d[c] - nb : 0u;
+        hi[c] = d[c] < na ? d[c] : na;
+    }
+    // C binary searches side by side
+    while (true) {
+        bool more = false;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (lo[c] < hi[c]) {
+                const uint32_t mid = (lo[c] + hi[c]) >> 1;
+                const K x = s_k[lds_slot<PAD_ITEMS>(base + mid)];
+                const K y = s_k[lds_slot<PAD_ITEMS>(base + na + d[c] - 1 - mid)];
+                if (x <= y)
+                    lo[c] = mid + 1;
+                else
+                    hi[c] = mid;
+                more |= lo[c] < hi[c];
+            }
+        }
+        if (!more)
+            break;
+    }
+    uint32_t ia[C], ib[C];
+    K a[C], b[C];
+    const uint32_t ea = base + na, eb = base + total;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        ia[c] = base + lo[c];
+        ib[c] = base + na + (d[c] - lo[c]);
+        a[c] = ia[c] < ea ? s_k[lds_slot<PAD_ITEMS>(ia[c])] : (K)0;
+        b[c] = ib[c] < eb ? s_k[lds_slot<PAD_ITEMS>(ib[c])] : (K)0;
+    }
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const bool take_a = ib[c] >= eb || (ia[c] < ea && a[c] <= b[c]);
+            key[c * L + j] = take_a ? a[c] : b[c];
+            src[c * L + j] = take_a ? ia[c] : ib[c];
+            ia[c] += take_a;
+            ib[c] += !take_a;
+            const uint32_t nx = take_a ? ia[c] : ib[c];
+            const bool has = take_a ? ia[c] < ea : ib[c] < eb;
+            const K nk = has ? s_k[lds_slot<PAD_ITEMS>(nx)] : (K)0;
+            a[c] = take_a ? nk : a[c];
+            b[c] = take_a ? b[c] : nk;
+        }
     }
 }
 
@@ -127,7 +162,7 @@ struct MergeTileArgs {
     uint32_t map_store;  // key order undone on store (when no merge level follows)
 };
 
-template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS>
+template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS, int CHAINS>
 __global__ __launch_bounds__(THREADS) void k_merge_tile(MergeTileArgs a)
 {
     constexpr uint32_t T = THREADS * ITEMS;
@@ -193,13 +228,8 @@ __global__ __launch_bounds__(THREADS) void k_merge_tile(MergeTileArgs a)
         __syncthreads();
         const uint32_t o = t * ITEMS;          // first output of this thread
         const uint32_t pb = o & ~(2 * w - 1);  // its pair of runs
-        const uint32_t diag = o - pb;
-        const uint32_t i = merge_split<K>(
-            diag, w, w, [&](uint32_t x) { return s_k[lds_slot<ITEMS>(pb + x)]; },
-            [&](uint32_t y) { return s_k[lds_slot<ITEMS>(pb + w + y)]; });
         uint32_t src[ITEMS];
-        merge_serial<K, ITEMS, ITEMS>(s_k, pb + i, pb + w, pb + w + (diag - i), pb + 2 * w, key,
-                                      src);
+        merge_chains<K, ITEMS, CHAINS, ITEMS>(s_k, pb, w, w, o - pb, key, src);
         if constexpr (HAS_V) {
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j)
@@ -258,6 +288,12 @@ __device__ __forceinline__ PairRuns pair_runs(uint32_t g, uint32_t w, uint32_t n
     return p;
 }
 
+// One thread per split: a binary search for the first x in [lo, hi) with
+// A[x] > B[diag - 1 - x] (hi if none), the merge-path split of merge_chains.
+// Measured on MI355X, searches with several probes per step (8 per thread,
+// or 64 per wave) fetch so many more scattered lines that they take longer
+// than this one, whose deep probes mostly hit lines shared by neighbouring
+// splits.
 template <typename K, int TILE>
 __global__ __launch_bounds__(256) void k_merge_split(MergeLevelArgs a)
 {
@@ -270,13 +306,20 @@ __global__ __launch_bounds__(256) void k_merge_split(MergeLevelArgs a)
     const PairRuns p = pair_runs(g, a.w, a.n);
     const K *A = (const K *)a.sk + p.base;
     const K *B = A + a.w;
-    const uint32_t i = merge_split<K>(
-        g - p.base, p.na, p.nb, [&](uint32_t x) { return A[x]; },
-        [&](uint32_t y) { return B[y]; });
-    a.split[b] = p.base + i;
+    const uint32_t diag = g - p.base;
+    uint32_t lo = diag > p.nb ? diag - p.nb : 0u;
+    uint32_t hi = diag < p.na ? diag : p.na;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (A[mid] <= B[diag - 1 - mid])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    a.split[b] = p.base + lo;
 }
 
-template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS>
+template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS, int CHAINS>
 __global__ __launch_bounds__(THREADS) void k_merge_pass(MergeLevelArgs a)
 {
     constexpr uint32_t T = THREADS * ITEMS;
@@ -322,13 +365,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_pass(MergeLevelArgs a)
     K key[ITEMS];
     V val[HAS_V ? ITEMS : 1];
     uint32_t src[ITEMS];
-    {
-        const uint32_t d = min(o, ca + cb);
-        const uint32_t i = merge_split<K>(
-            d, ca, cb, [&](uint32_t x) { return s_k[lds_slot<ITEMS>(x)]; },
-            [&](uint32_t y) { return s_k[lds_slot<ITEMS>(ca + y)]; });
-        merge_serial<K, ITEMS, ITEMS>(s_k, i, ca, ca + (d - i), ca + cb, key, src);
-    }
+    merge_chains<K, ITEMS, CHAINS, ITEMS>(s_k, 0, ca, cb, min(o, ca + cb), key, src);
     if constexpr (HAS_V) {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j)

@@ -9,7 +9,7 @@ struct MergeLaunch {
     using S = MergeShape<K, HAS_V>;
     static void tile_sort(const MergeTileArgs &a, uint32_t grid, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_merge_tile<K, K, HAS_V, S::kTileThreads, S::kItems>), dim3(grid),
+        hipLaunchKernelGGL((k_merge_tile<K, K, HAS_V, S::kTileThreads, S::kTileItems, S::kTileChains>), dim3(grid),
                            dim3(S::kTileThreads), 0, s, a);
     }
     static void split(const MergeLevelArgs &a, uint32_t grid, hipStream_t s)
@@ -18,7 +18,7 @@ struct MergeLaunch {
     }
     static void pass(const MergeLevelArgs &a, uint32_t grid, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_merge_pass<K, K, HAS_V, S::kPassThreads, S::kItems>), dim3(grid),
+        hipLaunchKernelGGL((k_merge_pass<K, K, HAS_V, S::kPassThreads, S::kPassItems, S::kPassChains>), dim3(grid),
                            dim3(S::kPassThreads), 0, s, a);
     }
     static MergeOps ops() { return MergeOps{S::kTile, S::kPassTile, &tile_sort, &split, &pass}; }

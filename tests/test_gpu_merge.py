@@ -13,7 +13,7 @@ from tests.certify import certify_stable_sort
 pytestmark = pytest.mark.gpu
 
 TILE = 8192       # elements per tile sort
-PASS_TILE = 4096  # outputs per merge-pass workgroup
+PASS_TILE = 2048  # outputs per merge-pass workgroup
 SIZES = [1, 2, 3, 100, TILE - 1, TILE, TILE + 1, 2 * TILE + 5, 3 * PASS_TILE + 17,
          5 * TILE + 3, 100003, (1 << 18) + (1 << 17) + 7]
 KINDS = [(32, False), (32, True), (64, False), (64, True)]
