@@ -6,7 +6,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 
 The arithmetic lives in plain C compiled with gcc: ``lsd_oracle.c``, a
 stable counting-sort LSD radix sort written from the paper's description
-(Section 2.6), and ``merge_oracle.c``, the stable merge sort of Section 2.4.
+(Section 2.6), ``merge_oracle.c``, the stable merge sort of Section 2.4, and
+``bitonic_oracle.c``, Batcher's bitonic network of Section 2.1.
 This module only marshals numpy arrays into them (and holds the key-order
 maps, written in numpy from their definitions).
 """
@@ -19,7 +20,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "lsd_oracle.c"), os.path.join(_HERE, "merge_oracle.c")]
+_SRCS = [os.path.join(_HERE, "lsd_oracle.c"), os.path.join(_HERE, "merge_oracle.c"),
+         os.path.join(_HERE, "bitonic_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -46,8 +48,11 @@ def _load():
         lib.oracle_digit_histograms.argtypes = [vp, u64, ci, ci, vp]
         lib.oracle_segmented_sort.argtypes = [ci, vp, vp, vp, u64, ci]
         lib.oracle_merge_sort.argtypes = [ci, vp, vp, u64, u64, ci]
+        lib.oracle_bitonic_sort.argtypes = [ci, vp, vp, u64]
+        lib.oracle_bitonic_network.argtypes = [vp, u64]
         for f in (lib.oracle_sort_u32, lib.oracle_sort_u64, lib.oracle_digit_histograms,
-                  lib.oracle_segmented_sort, lib.oracle_merge_sort):
+                  lib.oracle_segmented_sort, lib.oracle_merge_sort, lib.oracle_bitonic_sort,
+                  lib.oracle_bitonic_network):
             f.restype = ci
         _lib = lib
     return _lib
@@ -118,6 +123,43 @@ def merge_sort(keys, vals=None, tile: int = 1, levels: int = -1):
     bits = 32 if k.dtype == np.uint32 else 64
     if _load().oracle_merge_sort(bits, _ptr(k), _ptr(v), k.size, tile, levels) != 0:
         raise ValueError("oracle rejected the arguments")
+    return k, v
+
+
+def bitonic_sort(keys, vals=None):
+    """Batcher's bitonic network (paper, Section 2.1) over the next power of
+    two, on (key, input index) pairs: the stable sort by unsigned key."""
+    keys, vals = _check_pair(keys, vals)
+    k = np.array(keys, copy=True, order="C")
+    v = None if vals is None else np.array(vals, copy=True, order="C")
+    bits = 32 if k.dtype == np.uint32 else 64
+    if _load().oracle_bitonic_sort(bits, _ptr(k), _ptr(v), k.size) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return k, v
+
+
+def bitonic_network(words):
+    """The bare network (no index tie-break) on a power-of-two number of
+    uint64 words."""
+    w = np.array(words, dtype=np.uint64, copy=True, order="C")
+    if _load().oracle_bitonic_network(_ptr(w), w.size) != 0:
+        raise ValueError("oracle rejected the arguments")
+    return w
+
+
+def segmented_bitonic_sort(keys, vals, offsets):
+    """bitonic_sort of every segment [offsets[s], offsets[s+1]) on its own."""
+    keys, vals = _check_pair(keys, vals)
+    k = np.array(keys, copy=True, order="C")
+    v = None if vals is None else np.array(vals, copy=True, order="C")
+    off = np.asarray(offsets, dtype=np.uint64)
+    for a, b in zip(off[:-1], off[1:]):
+        a, b = int(a), int(b)
+        if b > a:
+            ks, vs = bitonic_sort(k[a:b], None if v is None else v[a:b])
+            k[a:b] = ks
+            if v is not None:
+                v[a:b] = vs
     return k, v
 
 
