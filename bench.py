@@ -161,6 +161,9 @@ def parse():
                     help="segmented workload: number of segments")
     ap.add_argument("--seg-log2", default="4,20",
                     help="segmented workload: log2 of the smallest and largest segment size")
+    ap.add_argument("--tiny-cap", type=int, default=-1,
+                    help="segmented workload: segments of 2..cap elements go to the bitonic "
+                         "network (0: to the radix block sort; -1: the library default)")
     ap.add_argument("--per-segment-steps", type=int, default=1,
                     help="segmented workload: timed steps of the one-sort-per-segment form "
                          "(0 skips it)")
@@ -342,6 +345,9 @@ def bench_segmented(args, torch, rs, datagen, dev):
     ko = torch.empty_like(kd)
     vo = torch.empty_like(vd)
     ctx = rs.context(0)
+    if args.tiny_cap >= 0:
+        ctx.tiny_cap(args.tiny_cap)
+    tiny_cap = ctx.tiny_cap()
     tuning = None
     if not args.no_tune:
         # the autotuner times every configuration on this batch and selects
@@ -426,6 +432,18 @@ def bench_segmented(args, torch, rs, datagen, dev):
                     "kernel": "k_seg_pass_u32", "avg_launch_ms": round(avg, 5),
                     "launches": len(pass_ms), "bytes_per_launch": bpl,
                     "elements_in_large_segments": int(large.sum())}
+    tiny = sizes[(sizes > 1) & (sizes <= tiny_cap)]
+    tiny_ms = kern.get("k_seg_bitonic", [])
+    tiny_roofline = None
+    if tiny_ms and tiny.size:
+        avg = sum(tiny_ms) / len(tiny_ms)
+        bpl = 2 * int(tiny.sum()) * 8  # read and write every key and value once
+        achieved = bpl / (avg * 1e-3) / 1e9
+        tiny_roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "kernel": "k_seg_bitonic", "avg_launch_ms": round(avg, 5),
+                         "launches": len(tiny_ms), "bytes_per_launch": bpl,
+                         "segments": int(tiny.size), "elements": int(tiny.sum())}
     out = {
         "metric": "Mkeys/s, batched segmented sort vs one launch per segment",
         "value": round(total / batched_ms / 1e3, 1),
@@ -439,8 +457,10 @@ def bench_segmented(args, torch, rs, datagen, dev):
                                f"uniform keys, value = index in segment; MT19937 seed 1",
                    "segments": S, "total_elements": total,
                    "elements_in_large_segments": int(large.sum()),
+                   "tiny_cap": tiny_cap,
                    "segments_by_class": {"le1": int((sizes <= 1).sum()),
-                                         "small_le4096": int(((sizes > 1) & (sizes <= 4096)).sum()),
+                                         "tiny_bitonic": int(tiny.size),
+                                         "small_le4096": int(((sizes > max(1, tiny_cap)) & (sizes <= 4096)).sum()),
                                          "medium_le16384": int(((sizes > 4096) & (sizes <= 16384)).sum()),
                                          "large": int(large.size)}},
         "batched_ms": round(batched_ms, 3),
@@ -452,6 +472,7 @@ def bench_segmented(args, torch, rs, datagen, dev):
         "hbm_frac_whole_batch": round(4 * 2 * total * 8 / (batched_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "kernels_ms": kern_ms,
         "roofline": roofline,
+        "tiny_roofline": tiny_roofline,
         "kernel_config": dict(cfg, index=cfg_index),
         "tuning": tuning,
         "host_generation_s": round(gen_s, 1),

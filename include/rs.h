@@ -197,6 +197,19 @@ rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_
                                   uint64_t total, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Tiny segments of a segmented sort.  Segments of 2 .. cap elements (cap at
+ * most 1024; the default is 1024) are sorted by one wave each with Batcher's
+ * bitonic network (Section 2.1) in registers, on (key, position in the
+ * segment) pairs so that the result is the same stable sort as the radix
+ * path's; cap 0 (or 1) sends them to the one-workgroup radix sort instead.
+ * The setting belongs to the context and applies to later
+ * rs_segmented_sort* calls and to graphs captured after it.
+ * cap > 1024 -> RS_ERR_INVALID_ARGUMENT.
+ */
+rs_status rs_segmented_tiny_cap_set(rs_context *ctx, uint32_t cap);
+rs_status rs_segmented_tiny_cap_get(const rs_context *ctx, uint32_t *cap);
+
+/*
  * Stable merge sort (Section 2.4: the sequence is cut into runs, each run is
  * sorted, and sorted runs are merged pairwise with a stable merge until one
  * run remains), the comparison-based counterpart of the radix sort.  Same

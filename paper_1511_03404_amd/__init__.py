@@ -47,6 +47,7 @@ EXPORTED = (
     "rs_profile_enable", "rs_profile_tag", "rs_profile_reset", "rs_profile_read",
     "rs_config_count", "rs_config_get", "rs_tune_set", "rs_tune_get",
     "rs_sort", "rs_segmented_sort_order", "rs_merge_sort", "rs_merge_workspace_bytes",
+    "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get",
 )
 
 
@@ -108,13 +109,16 @@ def lib():
                                                   sz, vp]
             L.rs_merge_sort.argtypes = [vp, ci, u32, vp, vp, vp, vp, u64, vp, sz, vp]
             L.rs_merge_workspace_bytes.argtypes = [vp, ci, ci, u64, ctypes.POINTER(sz)]
+            L.rs_segmented_tiny_cap_set.argtypes = [vp, u32]
+            L.rs_segmented_tiny_cap_get.argtypes = [vp, ctypes.POINTER(u32)]
             for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
                          "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
                          "rs_segmented_sort", "rs_segmented_workspace_bytes",
                          "rs_profile_enable", "rs_profile_tag", "rs_profile_reset",
                          "rs_profile_read", "rs_config_count", "rs_config_get",
                          "rs_tune_set", "rs_tune_get", "rs_sort", "rs_segmented_sort_order",
-                         "rs_merge_sort", "rs_merge_workspace_bytes"):
+                         "rs_merge_sort", "rs_merge_workspace_bytes",
+                         "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get"):
                 getattr(L, name).restype = ci
             _lib = L
     return _lib
@@ -152,6 +156,16 @@ class Context:
         out = ctypes.c_size_t()
         kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
         _check(lib().rs_workspace_bytes(self.handle, kt, int(has_values), n, ctypes.byref(out)))
+        return out.value
+
+    def tiny_cap(self, cap: int | None = None) -> int:
+        """Segments of 2 .. cap elements are sorted by a bitonic network per
+        wave (cap <= 1024, 0 sends them to the one-workgroup radix sort).
+        Sets the cap if given; returns the cap in force."""
+        if cap is not None:
+            _check(lib().rs_segmented_tiny_cap_set(self.handle, int(cap)))
+        out = ctypes.c_uint32()
+        _check(lib().rs_segmented_tiny_cap_get(self.handle, ctypes.byref(out)))
         return out.value
 
     def merge_workspace_bytes(self, key_bits: int, has_values: bool, n: int) -> int:

@@ -1,6 +1,10 @@
 // Batched segmented sort: many independent stable LSD radix sorts (paper,
 // Section 2.6) of uneven sizes in one enqueue, classified on the device:
 //   * size 0 or 1           -- nothing to sort (a single element is copied);
+//   * size <= tiny cap      -- one wave sorts it in registers with a bitonic
+//                              network on (key, position) pairs (Section 2.1,
+//                              k_seg_bitonic in rs_bitonic.h; the cap is a
+//                              context setting, 0 turns the class off);
 //   * size <= small cap     -- one workgroup sorts it in LDS (k_block_sort,
 //                              small shape, several workgroups per CU);
 //   * size <= medium cap    -- the same with the medium shape;
@@ -30,6 +34,8 @@ constexpr int kSegSmallClaim = 4;
 constexpr int kSegMediumClaim = 5;
 constexpr int kSegHistClaim = 6;
 constexpr int kSegError = 7;        // bit 0: a segment of 2^30+ elements; bit 1: tiles overflow
+constexpr int kSegTinyLen = 8;
+constexpr int kSegTinyClaim = 9;
 constexpr int kSegPassCounter = 32; // [32, 48): group counter per pass
 constexpr int kSegChunks = 16;      // histogram chunks of the large segments
 constexpr int kSegChunkClaim = 17;
@@ -45,6 +51,7 @@ struct SegClassifyArgs {
     uint64_t total;
     uint32_t max_tiles;
     uint32_t *ctrl;
+    SegRange *tiny_list;
     SegRange *small_list;
     SegRange *medium_list;
     SegLarge *large;
@@ -55,6 +62,7 @@ struct SegClassifyArgs {
     const void *vin;
     void *kout;
     void *vout;
+    uint32_t tiny_cap;  // 0: no tiny class
     uint32_t small_cap;
     uint32_t medium_cap;
     uint32_t tile;
@@ -76,6 +84,8 @@ __global__ __launch_bounds__(256) void k_seg_classify(SegClassifyArgs a)
             ((K *)a.kout)[start] = ((const K *)a.kin)[start];
             if constexpr (HAS_V)
                 ((K *)a.vout)[start] = ((const K *)a.vin)[start];
+        } else if (size <= a.tiny_cap) {
+            a.tiny_list[atomicAdd(&a.ctrl[kSegTinyLen], 1u)] = SegRange{start, (uint32_t)size, 0};
         } else if (size <= a.small_cap) {
             a.small_list[atomicAdd(&a.ctrl[kSegSmallLen], 1u)] = SegRange{start, (uint32_t)size, 0};
         } else if (size <= a.medium_cap) {

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "rs.h"
+#include "rs_bitonic.h"
 #include "rs_block.h"
 #include "rs_configs.h"
 #include "rs_device.h"
@@ -101,6 +102,8 @@ struct rs_context {
     // tune table: configuration index per [64-bit keys][values][segmented]
     // [ceil(log2 n)], -1 = the default (index 0)
     int8_t tune[2][2][2][kTuneClasses];
+    // segments of 2 .. tiny_cap elements go to the bitonic network (0: none)
+    uint32_t tiny_cap = kTinyMax;
     rs_context() { memset(tune, -1, sizeof tune); }
 };
 
@@ -597,8 +600,8 @@ struct SegLayout {
     uint64_t max_tiles;
     uint64_t claim_words;
     uint64_t max_chunks;
-    uint64_t off_ctrl, off_small, off_medium, off_large, off_base, off_tile_seg, off_status,
-        status_bytes, off_tmp_k, off_tmp_v, total;
+    uint64_t off_ctrl, off_tiny, off_small, off_medium, off_large, off_base, off_tile_seg,
+        off_status, status_bytes, off_tmp_k, off_tmp_v, total;
     uint64_t off_hist, off_chunk_seg;
 };
 
@@ -615,6 +618,8 @@ static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total,
     uint64_t o = 0;
     L.off_ctrl = o;
     o = align_up(o + kSegWords * 4, 256);
+    L.off_tiny = o;
+    o = align_up(o + (uint64_t)nseg * sizeof(SegRange), 256);
     L.off_small = o;
     o = align_up(o + (uint64_t)nseg * sizeof(SegRange), 256);
     L.off_medium = o;
@@ -695,6 +700,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     hipStream_t s = (hipStream_t)stream;
     char *wb = (char *)w;
     uint32_t *ctrl = (uint32_t *)(wb + L.off_ctrl);
+    SegRange *tiny_list = (SegRange *)(wb + L.off_tiny);
     SegRange *small_list = (SegRange *)(wb + L.off_small);
     SegRange *medium_list = (SegRange *)(wb + L.off_medium);
     SegLarge *large = (SegLarge *)(wb + L.off_large);
@@ -717,17 +723,30 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
         const uint32_t g = (uint32_t)std::min<uint64_t>(4096, (nvec + 255) / 256);
         hipLaunchKernelGGL(k_zero, dim3(std::max(1u, g)), dim3(256), 0, s, (uint4 *)status, nvec);
     });
-    SegClassifyArgs ca{offsets, nseg, total, (uint32_t)L.max_tiles, ctrl, small_list, medium_list,
-                       large, tile_seg, chunk_seg, (uint32_t)L.max_chunks, kin, vin, kout, vout,
-                       (uint32_t)B::kSmallCap, (uint32_t)B::kMediumCap, (uint32_t)op.tile};
+    SegClassifyArgs ca{offsets,   nseg,        total,     (uint32_t)L.max_tiles,
+                       ctrl,      tiny_list,   small_list, medium_list,
+                       large,     tile_seg,    chunk_seg, (uint32_t)L.max_chunks,
+                       kin,       vin,         kout,      vout,
+                       ctx->tiny_cap, (uint32_t)B::kSmallCap, (uint32_t)B::kMediumCap,
+                       (uint32_t)op.tile};
     launch(ctx, s, "k_seg_classify", [&] {
         const uint32_t g = std::min<uint32_t>(1024, (nseg + 255) / 256);
         hipLaunchKernelGGL((k_seg_classify<K, HAS_V>), dim3(std::max(1u, g)), dim3(256), 0, s, ca);
     });
-    // small and medium segments: persistent workgroups over the device lists
+    // tiny, small and medium segments: persistent workgroups over the device lists
     auto grid_of = [&](const void *kernel, int threads) {
         return resident_blocks(kernel, threads) * cus;
     };
+    if (ctx->tiny_cap > 0) {
+        TinyArgs ta{kin, vin, kout, vout, tiny_list, ctrl + kSegTinyLen, ctrl + kSegTinyClaim,
+                    kmap};
+        auto kern = k_seg_bitonic<K, K, HAS_V>;
+        const uint32_t g =
+            std::min<uint32_t>(grid_of((const void *)kern, 256), (nseg + 3) / 4);
+        launch(ctx, s, "k_seg_bitonic", [&] {
+            hipLaunchKernelGGL(kern, dim3(std::max(1u, g)), dim3(256), 0, s, ta);
+        });
+    }
     {
         BlockArgs ba{kin, vin, kout, vout, small_list, ctrl + kSegSmallLen, ctrl + kSegSmallClaim,
                      0, kmap};
@@ -1083,6 +1102,24 @@ rs_status rs_merge_sort(rs_context *ctx, rs_key_type key_type, uint32_t order,
                                          ws_bytes, stream, kmap);
     return run_merge<uint64_t, false>(ctx, (const uint64_t *)keys_in, nullptr,
                                       (uint64_t *)keys_out, nullptr, n, ws, ws_bytes, stream, kmap);
+}
+
+rs_status rs_segmented_tiny_cap_set(rs_context *ctx, uint32_t cap)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (cap > kTinyMax)
+        return fail(RS_ERR_INVALID_ARGUMENT, "tiny cap %u exceeds %u", cap, kTinyMax);
+    ctx->tiny_cap = cap < 2 ? 0u : cap;
+    return RS_OK;
+}
+
+rs_status rs_segmented_tiny_cap_get(const rs_context *ctx, uint32_t *cap)
+{
+    if (!ctx || !cap)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx or cap is NULL");
+    *cap = ctx->tiny_cap;
+    return RS_OK;
 }
 
 rs_status rs_config_count(rs_key_type key_type, int has_values, int *count)

@@ -243,3 +243,14 @@ def test_merge_sort_argument_errors(rs, ctx):
                            fake + (1 << 22), 100000, ws, need - 1, None) \
         == rs.RS_ERR_INVALID_ARGUMENT
     assert b"workspace" in L.rs_last_error()
+
+
+def test_tiny_cap_setting(rs, ctx):
+    L = rs.lib()
+    assert ctx.tiny_cap() == 1024
+    assert ctx.tiny_cap(0) == 0
+    assert ctx.tiny_cap(1) == 0  # a cap below 2 turns the class off
+    assert ctx.tiny_cap(777) == 777
+    assert L.rs_segmented_tiny_cap_set(ctx.handle, 1025) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_segmented_tiny_cap_set(None, 8) == rs.RS_ERR_INVALID_ARGUMENT
+    assert ctx.tiny_cap() == 777
