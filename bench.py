@@ -37,10 +37,9 @@ COPY_CALIB_BYTES = 1 << 30  # plain copy used to calibrate the HBM byte counters
 
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-# the sources of the digit-pass kernel: counter readings taken on other
-# sources are stale
-KERNEL_SOURCES = ("paper_1511_03404_amd/csrc/rs_kernels.h", "paper_1511_03404_amd/csrc/rs_device.h",
-                  "paper_1511_03404_amd/csrc/rs_segmented.h")
+# the sources the digit-pass kernel is compiled from: counter readings taken
+# on other sources are stale
+KERNEL_SOURCES = ("paper_1511_03404_amd/csrc/rs_kernels.h", "paper_1511_03404_amd/csrc/rs_device.h")
 MERGE_SOURCES = ("paper_1511_03404_amd/csrc/rs_merge.h", "paper_1511_03404_amd/csrc/rs_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
