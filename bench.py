@@ -173,6 +173,12 @@ def parse():
                     help="merge workload: the kind and size of the radix workload of that name")
     ap.add_argument("--grid-max-log2", type=int, default=25,
                     help="grid workload: largest log2 size (64-bit kinds stop one lower)")
+    ap.add_argument("--grid-min-log2", type=int, default=15,
+                    help="grid workload: smallest log2 size")
+    ap.add_argument("--grid-tune", action="store_true",
+                    help="grid workload: autotune each kind and size class before timing it")
+    ap.add_argument("--grid-graph", action="store_true",
+                    help="grid workload: also time each point replayed from a captured HIP graph")
     ap.add_argument("--grid-oracle-max-log2", type=int, default=22,
                     help="grid workload: time the oracle up to this log2 size (speedup column)")
     return ap.parse_args()
@@ -263,7 +269,7 @@ def bench_grid(args, torch, rs, datagen, dev):
     the speedup up to --grid-oracle-max-log2."""
     import oracle
     sizes = []
-    for k in range(15, args.grid_max_log2 + 1):
+    for k in range(args.grid_min_log2, args.grid_max_log2 + 1):
         sizes.append(1 << k)
         if k < args.grid_max_log2:
             sizes.append((1 << k) + (1 << (k - 1)))
@@ -276,6 +282,10 @@ def bench_grid(args, torch, rs, datagen, dev):
         for n in sizes:
             if n > (1 << limit):
                 continue
+            tuned = None
+            if args.grid_tune:
+                from paper_1511_03404_amd import tune
+                tuned = tune.tune_sort(bits, has_v, n, ctx=ctx, reps=5, warmup=1)["index"]
             ws = torch.empty(ctx.workspace_bytes(bits, has_v, n), dtype=torch.uint8, device=dev)
             for d in datagen.DISTRIBUTIONS:
                 kh = datagen.keys(d, n, bits, seed=1)
@@ -299,7 +309,25 @@ def bench_grid(args, torch, rs, datagen, dev):
                 ev1.synchronize()
                 ms = ev0.elapsed_time(ev1) / args.steps
                 pt = {"kind": kind, "dist": d, "n": n, "ms": round(ms, 5),
-                      "Mkeys_s": round(n / ms / 1e3, 1)}
+                      "Mkeys_s": round(n / ms / 1e3, 1),
+                      "config": ctx.tune_get(bits, has_v, False, rs.size_class(n))}
+                if args.grid_graph:
+                    # the same sort captured once and replayed: the launches
+                    # are submitted together, so small sizes lose their host
+                    # launch gaps
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g):
+                        go()
+                    g.replay()
+                    ev0.record()
+                    for _ in range(args.steps):
+                        g.replay()
+                    ev1.record()
+                    ev1.synchronize()
+                    gms = ev0.elapsed_time(ev1) / args.steps
+                    pt["graph_ms"] = round(gms, 5)
+                    pt["graph_Mkeys_s"] = round(n / gms / 1e3, 1)
+                    del g
                 if n <= (1 << args.grid_oracle_max_log2):
                     t0 = time.perf_counter()
                     oracle.sort(kh, vh)
@@ -318,7 +346,8 @@ def bench_grid(args, torch, rs, datagen, dev):
         "config": {"workload": "grid: u32/u64 keys and pairs x 6 distributions x n = 2^15.."
                                f"2^{args.grid_max_log2} and 2^k+2^(k-1); value = mean over the six "
                                f"distributions of u32 pairs at 2^{args.grid_max_log2}",
-                   "sizes": sizes},
+                   "sizes": sizes, "graph_replay": bool(args.grid_graph),
+                   "tuned_per_size": bool(args.grid_tune)},
         "oracle_cores": 1,
         "points": points,
     }

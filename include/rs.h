@@ -263,17 +263,21 @@ rs_status rs_config_count(rs_key_type key_type, int has_values, int *count);
 rs_status rs_config_get(rs_key_type key_type, int has_values, int index, rs_config *config);
 
 /*
- * Select configuration `index` (-1 = the default) for sorts of this kind
- * whose size class ceil(log2 n) is size_log2 (0..39), or for every size
- * class if size_log2 is -1.  segmented != 0 selects the table of
- * rs_segmented_sort.  Takes effect for calls enqueued afterwards; a
- * workspace sized before the change may be too small for the new choice
- * (the sort then returns RS_ERR_INVALID_ARGUMENT).
+ * Select configuration `index` (-1 = the built-in choice) for sorts of this
+ * kind whose size class ceil(log2 n) is size_log2 (0..39), or for every
+ * size class if size_log2 is -1.  segmented != 0 selects the table of
+ * rs_segmented_sort.  The built-in choice of a plain sort is the one the
+ * autotuner selected on MI355X: 1024 x 8 tiles up to size class 21 (24 for
+ * 64-bit pairs), 256 x 16 or 512 x 8 tiles at the smallest classes of some
+ * kinds, index 0 above; segmented sorts use index 0.  Takes effect for
+ * calls enqueued afterwards; a workspace sized before the change may be too
+ * small for the new choice (the sort then returns RS_ERR_INVALID_ARGUMENT).
  */
 rs_status rs_tune_set(rs_context *ctx, rs_key_type key_type, int has_values, int segmented,
                       int size_log2, int index);
 
-/* The configuration index the table selects for one size class (0..39). */
+/* The configuration index in force for one size class (0..39): the table's
+ * entry, or the built-in choice where it is unset. */
 rs_status rs_tune_get(const rs_context *ctx, rs_key_type key_type, int has_values, int segmented,
                       int size_log2, int *index);
 

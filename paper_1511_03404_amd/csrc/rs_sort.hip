@@ -128,12 +128,47 @@ static const SegOps *seg_table(int key_bytes, bool has_values, int *count)
 
 // The configuration the context's tune table selects (the first one of the
 // table unless set otherwise).
+// The configuration a size class gets when its table entry is unset: what
+// the autotuner selected on MI355X for plain sorts of uniform keys.  Tiles
+// of 8192 elements (1024 x 8) up to 2^21 elements (2^24 for 64-bit pairs):
+// a small sort has few tiles, and a tile's latency, not HBM, sets the pass
+// time; tiles of 4096 at the smallest sizes of some kinds; the list's
+// default (index 0) above.  Looked up by shape, so a different list falls
+// back to index 0.
+static int default_index(int key_bytes, bool has_values, bool segmented, int c)
+{
+    if (segmented)
+        return 0;
+    int threads = 0, items = 0;
+    if (key_bytes == 8 && has_values) {
+        if (c <= 17)
+            threads = 512, items = 8;
+        else if (c <= 24)
+            threads = 1024, items = 8;
+    } else if (c <= 15 && (has_values || key_bytes == 8)) {
+        threads = 256, items = 16;
+    } else if (c <= 21) {
+        threads = 1024, items = 8;
+    }
+    if (threads == 0)
+        return 0;
+    int count = 0;
+    const SortOps *t = sort_table(key_bytes, has_values, &count);
+    for (int i = 0; i < count; ++i)
+        if (t[i].r == 8 && t[i].threads == threads && t[i].items == items)
+            return i;
+    return 0;
+}
+
 static int tuned_index(const rs_context *ctx, int key_bytes, bool has_values, bool segmented,
                        uint64_t n, int count)
 {
     const int c = std::min(size_class(n), kTuneClasses - 1);
     const int i = ctx->tune[key_bytes == 8][has_values][segmented][c];
-    return (i >= 0 && i < count) ? i : 0;
+    if (i >= 0 && i < count)
+        return i;
+    const int d = default_index(key_bytes, has_values, segmented, c);
+    return d < count ? d : 0;
 }
 
 static const SortOps &pick_sort(const rs_context *ctx, int key_bytes, bool has_values, uint64_t n)
@@ -1182,9 +1217,10 @@ rs_status rs_tune_get(const rs_context *ctx, rs_key_type key_type, int has_value
         return fail(RS_ERR_INVALID_ARGUMENT, "size_log2 %d outside [0, %d)", size_log2,
                     kTuneClasses);
     int count = 0;
-    (void)sort_table(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, &count);
+    const int kb = key_type == RS_KEY_U32 ? 4 : 8;
+    (void)sort_table(kb, has_values != 0, &count);
     const int i = ctx->tune[key_type == RS_KEY_U64][has_values != 0][segmented != 0][size_log2];
-    *index = (i >= 0 && i < count) ? i : 0;
+    *index = (i >= 0 && i < count) ? i : default_index(kb, has_values != 0, segmented != 0, size_log2);
     return RS_OK;
 }
 

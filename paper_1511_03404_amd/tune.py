@@ -66,15 +66,15 @@ def _candidates(key_bits, has_values, candidates):
     return cfgs, idx
 
 
-# a configuration replaces the default only if it is faster by this fraction:
-# ties would otherwise flip the choice from one run to the next
+# a configuration replaces the built-in choice only if it is faster by this
+# fraction: ties would otherwise flip the choice from one run to the next
 MARGIN = 0.03
 
 
-def _result(key_bits, has_values, segmented, n, cls, cfgs, times, note=None):
+def _result(key_bits, has_values, segmented, n, cls, cfgs, times, note=None, default=0):
     best = min(times, key=times.get)
-    if 0 in times and times[0] <= times[best] * (1.0 + MARGIN):
-        best = 0
+    if default in times and times[default] <= times[best] * (1.0 + MARGIN):
+        best = default
     r = {"key_bits": key_bits, "has_values": bool(has_values), "segmented": bool(segmented),
          "size_log2": cls, "n": int(n), "index": best, "config": cfgs[best],
          "ms": {str(i): round(t, 5) for i, t in sorted(times.items())}}
@@ -102,6 +102,8 @@ def tune_sort(key_bits: int, has_values: bool, n: int, ctx: Context | None = Non
     ko = torch.empty_like(keys)
     vo = torch.empty_like(keys) if has_values else None
     prev = ctx.tune_get(key_bits, has_values, False, cls)
+    ctx.tune_set(key_bits, has_values, False, cls, -1)
+    default = ctx.tune_get(key_bits, has_values, False, cls)  # the built-in choice
     need = 0
     for i in idx:
         ctx.tune_set(key_bits, has_values, False, cls, i)
@@ -115,7 +117,7 @@ def tune_sort(key_bits: int, has_values: bool, n: int, ctx: Context | None = Non
         else:
             fn = lambda: sort_keys(keys, ko, ctx=ctx, workspace=ws)  # noqa: E731
         times[i] = _median_ms(fn, reps, warmup)
-    res = _result(key_bits, has_values, False, n, cls, cfgs, times)
+    res = _result(key_bits, has_values, False, n, cls, cfgs, times, default=default)
     ctx.tune_set(key_bits, has_values, False, cls, res["index"] if apply else prev)
     return res
 
