@@ -119,7 +119,11 @@ rs_status rs_sort_pairs_u64(rs_context *ctx, const uint64_t *keys_in, const uint
  * every segment are left untouched in *_out.  Bytes of scratch:
  * rs_segmented_workspace_bytes().  Offsets are read on the device only (no
  * host round trip); a non-monotone offsets array is not detected and gives
- * unspecified (but in-bounds) results.
+ * unspecified (but in-bounds) results.  Segments are classified on the
+ * device: up to the tiny cap (rs_segmented_tiny_cap_set, 1024 by default) a
+ * bitonic network per wave (Section 2.1), up to 16384 elements (8192 for
+ * 64-bit pairs) a one-workgroup LDS radix sort, larger ones batched digit
+ * passes (Section 2.6); every class gives the same stable sort.
  */
 rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *keys_in,
                             const void *vals_in, void *keys_out, void *vals_out,
