@@ -107,8 +107,10 @@ def summarize_pmc(root):
                           f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB",
            "workloads": {}}
     import paper_1511_03404_amd as rs
-    for w, (_, bits, has_v, _) in WORKLOADS.items():
-        cfg = rs.configs(bits, has_v)[0]  # the counter runs use the default configuration
+    ctx = rs.Context(0)  # host-side only: the built-in configuration per size class
+    for w, (n, bits, has_v, _) in WORKLOADS.items():
+        # the counter runs skip the tuner: the built-in configuration of this size
+        cfg = rs.configs(bits, has_v)[ctx.tune_get(bits, has_v, False, rs.size_class(n))]
         k = pass_kernel_name(bits, has_v, cfg)
         fp = os.path.join(root, w, "FETCH_SIZE", "run_counter_collection.csv")
         wp = os.path.join(root, w, "WRITE_SIZE", "run_counter_collection.csv")

@@ -531,6 +531,22 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
     }
     const uint32_t excl = bins_exclusive_scan<NB>(cnt, L.tmp);
     if (t < NB) {
+        // tile-local offsets: wave offset + the digit's start in the tile
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww)
+            L.wcnt[ww * NB + t] += excl;
+    }
+    __syncthreads();
+    // stage the keys in rank order; the digit owners first look back (the
+    // other waves stage meanwhile), since only the global base needs it
+    if (t >= NB) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            rank[j] += wc[digit_of<R>(key[j], shift)];  // position in the tile
+            s_k[rank[j]] = key[j];
+        }
+    }
+    if (t < NB) {
         // decoupled look-back: read LBW predecessors per round trip, add
         // their counts in order up to the first inclusive one; on a tile
         // that has not published yet, wait and re-read from there
@@ -569,19 +585,15 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         L.gbase[t] = dbase + prefix - excl;
 #pragma unroll
-        for (int ww = 0; ww < W; ++ww)
-            L.wcnt[ww * NB + t] += excl;
+        for (int j = 0; j < ITEMS; ++j) {
+            rank[j] += wc[digit_of<R>(key[j], shift)];
+            s_k[rank[j]] = key[j];
+        }
     }
     __syncthreads();
 
-    // place: stage the keys in rank order, then write each digit run out
-    // with consecutive lanes on consecutive addresses; then the values
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        rank[j] += wc[digit_of<R>(key[j], shift)];  // position in the tile
-        s_k[rank[j]] = key[j];
-    }
-    __syncthreads();
+    // place: write each digit run out with consecutive lanes on consecutive
+    // addresses; then the values
     uint32_t dst[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
