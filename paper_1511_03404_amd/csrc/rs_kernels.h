@@ -449,8 +449,11 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
     }
 }
 
-// LDS of one digit pass.
-template <typename K, typename C>
+// LDS of one digit pass: the per-wave counters, the digits' global bases and
+// the staging buffers of the keys (which hold the lane-mask tables while
+// ranking) and of the values, so both are staged in one step and written out
+// after one barrier.
+template <typename K, typename C, bool HAS_V>
 struct PassLds {
     static constexpr int W = C::kThreads / kWave;
     static constexpr size_t kStageBytes = (size_t)C::kTile * sizeof(K);
@@ -461,6 +464,7 @@ struct PassLds {
     uint32_t tmp[8];
     uint32_t tile;
     __attribute__((aligned(16))) unsigned char stage[kStageBytes];
+    __attribute__((aligned(16))) unsigned char stage_v[HAS_V ? kStageBytes : 16];
 
     // zero the counters and the lane-mask tables before a tile
     __device__ __forceinline__ void clear(uint32_t t)
@@ -479,7 +483,7 @@ struct PassLds {
 // digit-sorted sequence is dk/dv[i] for i < limit.  dbase (threads < 2^R) is
 // the digit's starting offset in that sequence.  Ends with a barrier.
 template <typename K, typename V, bool HAS_V, typename C>
-__device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V *tv, K *dk,
+__device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, const V *tv, K *dk,
                                           V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
                                           uint32_t first_tile, uint32_t *status, uint32_t dbase,
                                           int shift, bool ballot_rank, uint32_t map_load,
@@ -494,7 +498,7 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
     constexpr int LBW = C::kLookback;
     static_assert(sizeof(V) == sizeof(K), "values have the key's width");
     K *s_k = (K *)L.stage;
-    V *s_v = (V *)L.stage;
+    V *s_v = (V *)L.stage_v;
     uint64_t *s_mask = (uint64_t *)L.stage;
     const uint32_t t = threadIdx.x;
     const uint32_t w = t / kWave;
@@ -537,13 +541,16 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
             L.wcnt[ww * NB + t] += excl;
     }
     __syncthreads();
-    // stage the keys in rank order; the digit owners first look back (the
-    // other waves stage meanwhile), since only the global base needs it
+    // stage the keys and values in rank order; the digit owners first look
+    // back (the other waves stage meanwhile), since only the global base
+    // needs it
     if (t >= NB) {
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             rank[j] += wc[digit_of<R>(key[j], shift)];  // position in the tile
             s_k[rank[j]] = key[j];
+            if constexpr (HAS_V)
+                s_v[rank[j]] = val[j];
         }
     }
     if (t < NB) {
@@ -588,6 +595,8 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
         for (int j = 0; j < ITEMS; ++j) {
             rank[j] += wc[digit_of<R>(key[j], shift)];
             s_k[rank[j]] = key[j];
+            if constexpr (HAS_V)
+                s_v[rank[j]] = val[j];
         }
     }
     __syncthreads();
@@ -604,11 +613,6 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C> &L, const K *tk, const V
             store_at(dk, dst[i], map_out(k, map_store));
     }
     if constexpr (HAS_V) {
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            s_v[rank[j]] = val[j];
-        __syncthreads();
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
             if (dst[i] < limit)
@@ -622,7 +626,7 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
 {
     constexpr int THREADS = C::kThreads;
     constexpr int T = C::kTile;
-    __shared__ PassLds<K, C> L;
+    __shared__ PassLds<K, C, HAS_V> L;
 
     const uint32_t t = threadIdx.x;
     const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
@@ -802,7 +806,7 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
 {
     constexpr int T = C::kTile;
     constexpr uint32_t NB = C::kBins;
-    __shared__ PassLds<K, C> L;
+    __shared__ PassLds<K, C, HAS_V> L;
     const uint32_t t = threadIdx.x;
     PassArgs pa{};
     pa.ctrl = a.ctrl + (kSegPassCounter - kCtrlTileCounter);
