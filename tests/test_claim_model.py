@@ -7,8 +7,9 @@ The model keeps what decides progress and drops the arithmetic:
     k / G; the claim with k % G == 0 opens the group by taking the next id
     from a global counter and publishing it; other claims of the group wait
     for the id;
-  * a workgroup claims its first two tiles at the start, then one more
-    during every tile's look-back (two ahead);
+  * ahead = 0 is the shipped kernel: a workgroup claims one tile, processes
+    it, then claims the next; ahead = 2 is a claim-ahead schedule: two tiles
+    claimed at the start, then one more during every tile's look-back;
   * a tile's look-back can finish once every lower tile has been started
     (its aggregate is published when its holder ranks it; inclusive values
     follow by induction);
@@ -27,7 +28,7 @@ NO_TILE = -1
 
 
 class Model:
-    def __init__(self, xcds, wgs_per_xcd, tiles, group, ordered, seed):
+    def __init__(self, xcds, wgs_per_xcd, tiles, group, ordered, seed, ahead=2):
         self.rng = random.Random(seed)
         self.G = group
         self.tiles = tiles
@@ -42,7 +43,8 @@ class Model:
         for x in range(xcds):
             for _ in range(wgs_per_xcd):
                 self.wgs.append({"x": x, "held": [], "claim": None, "state": "prologue",
-                                 "cur": None, "need": 2, "done": False})
+                                 "cur": None, "need": max(ahead, 1), "done": False})
+        self.ahead = ahead
 
     # one claim is a small state machine: counter -> (open | wait) -> tile
     def claim_step(self, wg):
@@ -105,12 +107,15 @@ class Model:
                 return True
             wg["cur"] = t
             self.started[t] = True                # ranked: aggregate published
-            wg["need"] = 1                        # claim during the look-back
+            if self.ahead:
+                wg["need"] = 1                    # claim during the look-back
             return True
         t = wg["cur"]
         if all(self.started[:t]):
             self.finished[t] = True
             wg["cur"] = None
+            if not self.ahead:
+                wg["need"] = 1                    # claim the next tile now
             return True
         return False
 
@@ -151,9 +156,10 @@ SHAPES = [
 ]
 
 
+@pytest.mark.parametrize("ahead", [0, 2])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_ordered_opening_processes_every_tile(shape):
-    r = explore(True, range(200), **shape)
+def test_ordered_opening_processes_every_tile(shape, ahead):
+    r = explore(True, range(200), ahead=ahead, **shape)
     assert r == {"ok": 200, "deadlock": 0, "timeout": 0, "lost": 0}, r
 
 
