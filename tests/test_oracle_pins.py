@@ -293,3 +293,56 @@ def test_segmented_certificate_has_teeth(oracle_lib):
     k2, v2 = k.copy(), v.copy()
     v2[[i, i + 1]] = v2[[i + 1, i]]
     assert "unstable" in certify_segmented(keys, k2, v2, off)
+
+
+def _mix64(x):
+    """splitmix64's finalizer (a published 64-bit mixing function), on uint64 arrays."""
+    x = x.astype(np.uint64, copy=True)
+    with np.errstate(over="ignore"):
+        x ^= x >> np.uint64(30)
+        x *= np.uint64(0xBF58476D1CE4E5B9)
+        x ^= x >> np.uint64(27)
+        x *= np.uint64(0x94D049BB133111EB)
+        x ^= x >> np.uint64(31)
+    return x
+
+
+def multiset_hash(keys, vals=None):
+    """Order-independent hash of the multiset of (key, value) pairs: the sum
+    mod 2^64 of a mixed 64-bit word per pair."""
+    k = np.asarray(keys).astype(np.uint64)
+    h = _mix64(k)
+    if vals is not None:
+        with np.errstate(over="ignore"):
+            h = _mix64(h ^ (np.asarray(vals).astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)))
+    with np.errstate(over="ignore"):
+        return int(h.sum(dtype=np.uint64))
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
+def test_multiset_hash_preserved(oracle_lib, bits, dist):
+    """The output is a rearrangement of the input: the multiset hash of the
+    (key, value) pairs is the same before and after every oracle sort."""
+    n = (1 << 14) + 77
+    keys = datagen.keys(dist, n, bits, seed=5)
+    vals = datagen.values(n, bits)
+    want = multiset_hash(keys, vals)
+    for k, v in (oracle_lib.sort(keys, vals), oracle_lib.merge_sort(keys, vals),
+                 oracle_lib.bitonic_sort(keys[:4096], vals[:4096])):
+        ref = want if k.size == n else multiset_hash(keys[:4096], vals[:4096])
+        assert multiset_hash(k, v) == ref
+
+
+def test_multiset_hash_has_teeth(oracle_lib):
+    """A changed key, a duplicated pair or a pair split apart changes the hash."""
+    keys = datagen.keys("bucket", 5000, 32, seed=6)
+    vals = datagen.values(5000, 32)
+    k, v = oracle_lib.sort(keys, vals)
+    h = multiset_hash(k, v)
+    k2 = k.copy(); k2[17] ^= np.uint32(1)
+    assert multiset_hash(k2, v) != h
+    k3, v3 = k.copy(), v.copy(); k3[5], v3[5] = k3[6], v3[6]
+    assert multiset_hash(k3, v3) != h
+    v4 = v.copy(); v4[[3, 4000]] = v4[[4000, 3]]
+    assert multiset_hash(k, v4) != h or k[3] == k[4000]
