@@ -796,6 +796,10 @@ def main():
         "hbm_frac_whole_sort": round(whole_frac, 4),
         "roofline": roofline,
         "per_distribution": per,
+        "paper_context": {"hardware": "GeForce GTX670 (2 GB) and Intel Core i7-3770K at 3.5 GHz",
+                          "rates": None,
+                          "note": "the paper shows its radix-sort rates only in figures; its text "
+                                  "prints no number to compare with"},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(bits, has_v, dists,
