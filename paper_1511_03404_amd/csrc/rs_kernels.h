@@ -479,15 +479,16 @@ struct PassLds {
 // One tile of a digit pass (the paper's counting sort, Section 2.6, spread
 // over workgroups): rank, publish the tile's digit counts, decoupled
 // look-back over tiles [first_tile, tile), stage in LDS, write the digit
-// runs.  The tile's elements are tk/tv[0, valid); destination index i of the
+// runs.  after_lookback(t) runs in every thread once the look-back is done,
+// before the writes (the plain pass claims its next tile there).  The tile's elements are tk/tv[0, valid); destination index i of the
 // digit-sorted sequence is dk/dv[i] for i < limit.  dbase (threads < 2^R) is
 // the digit's starting offset in that sequence.  Ends with a barrier.
-template <typename K, typename V, bool HAS_V, typename C>
+template <typename K, typename V, bool HAS_V, typename C, typename Hook>
 __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, const V *tv, K *dk,
                                           V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
                                           uint32_t first_tile, uint32_t *status, uint32_t dbase,
                                           int shift, bool ballot_rank, uint32_t map_load,
-                                          uint32_t map_store)
+                                          uint32_t map_store, Hook &&after_lookback)
 {
     constexpr int R = C::kRadixBits;
     constexpr uint32_t NB = C::kBins;
@@ -600,6 +601,7 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
         }
     }
     __syncthreads();
+    after_lookback(t);
 
     // place: write each digit run out with consecutive lanes on consecutive
     // addresses; then the values
@@ -654,9 +656,12 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
     // this digit's starting offset, fetched early (used after the look-back)
     const uint32_t dbase = t < (uint32_t)C::kBins ? a.digit_base[t] : 0u;
     const uint32_t xcc = t == 0 ? xcc_id() : 0u;
+    // the next tile is claimed once the current tile's look-back is done:
+    // the claim's round trips overlap the writes, and the workgroup waits
+    // on nothing while it holds the claimed tile
+    if (t == 0)
+        L.tile = claim_tile<C::kGroup>(a, xcc);
     while (true) {
-        if (t == 0)
-            L.tile = claim_tile<C::kGroup>(a, xcc);
         L.clear(t);
         __syncthreads();
         const uint32_t tile = L.tile;
@@ -667,7 +672,10 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
         pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile,
                                   0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0,
                                   (plan & kPlanFirst) ? a.kmap : 0u,
-                                  (plan & kPlanLast) ? a.kmap : 0u);
+                                  (plan & kPlanLast) ? a.kmap : 0u, [&](uint32_t tt) {
+                                      if (tt == 0)
+                                          L.tile = claim_tile<C::kGroup>(a, xcc);
+                                  });
     }
 }
 
@@ -835,7 +843,7 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
                                   (K *)a.dst_k + rec.start,
                                   HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
                                   tile, rec.tile_start, a.status, dbase, a.shift, false,
-                                  a.map_load, a.map_store);
+                                  a.map_load, a.map_store, [](uint32_t) {});
     }
 }
 
