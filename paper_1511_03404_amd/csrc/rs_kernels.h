@@ -51,7 +51,7 @@ struct PassCfg {
     static constexpr int kThreads = THREADS;
     static constexpr int kItems = ITEMS;
     static constexpr int kTile = THREADS * ITEMS;
-    static constexpr int kLookback = 8;
+    static constexpr int kLookback = 4;  // predecessors read per look-back round trip
     static constexpr int kGroup = kClaimGroup;
     // waves that find their digit peers with ballots (VALU) instead of the
     // LDS lane-mask table: the two methods give the same masks, and splitting
