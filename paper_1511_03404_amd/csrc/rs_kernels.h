@@ -465,15 +465,6 @@ struct PassLds {
     uint32_t tile;
     __attribute__((aligned(16))) unsigned char stage[kStageBytes];
     __attribute__((aligned(16))) unsigned char stage_v[HAS_V ? kStageBytes : 16];
-
-    // zero the counters and the lane-mask tables before a tile
-    __device__ __forceinline__ void clear(uint32_t t)
-    {
-        for (int i = t; i < W * C::kBins; i += C::kThreads) {
-            wcnt[i] = 0;
-            ((uint64_t *)stage)[i] = 0;
-        }
-    }
 };
 
 // One tile of a digit pass (the paper's counting sort, Section 2.6, spread
@@ -507,6 +498,12 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
     const uint32_t off0 = w * (kWave * ITEMS) + lane;
     uint32_t *wc = L.wcnt + w * NB;
 
+    // this wave's counters and lane-mask table are its own: it clears them
+    // itself (after the previous tile's closing barrier), no barrier needed
+    for (uint32_t i = lane; i < NB; i += kWave) {
+        wc[i] = 0;
+        s_mask[w * NB + i] = 0;
+    }
     // load: item j of lane l is element j*64 + l of this wave's run
     K key[ITEMS];
     V val[HAS_V ? ITEMS : 1];
@@ -661,9 +658,10 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
     // on nothing while it holds the claimed tile
     if (t == 0)
         L.tile = claim_tile<C::kGroup>(a, xcc);
+    __syncthreads();
     while (true) {
-        L.clear(t);
-        __syncthreads();
+        // the claim made during the previous tile is visible after its
+        // closing barrier
         const uint32_t tile = L.tile;
         if (tile == kNoTile)
             break;
@@ -826,7 +824,6 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
     while (true) {
         if (t == 0)
             L.tile = claim_tile<C::kGroup>(pa, xcc);
-        L.clear(t);
         __syncthreads();
         const uint32_t tile = L.tile;
         if (tile == kNoTile)
