@@ -439,6 +439,14 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
             for (int j = 0; j < ITEMS; ++j)
                 val[j] = off0 + j * kWave < valid ? tv[off0 + j * kWave] : (V)0;
         }
+        // vmcnt(0) (expcnt and lgkmcnt left at their maximum): the loads
+        // above sit behind branches, so after this path joins the full one
+        // the compiler could not tell how many of them are still in flight
+        // and would wait for every load, values included, before ranking
+        // the first key.  Waiting here, on the partial tile only, keeps the
+        // full tile's waits per item: item j is ranked once its own key has
+        // arrived, while the values are still on their way.
+        __builtin_amdgcn_s_waitcnt(0xF70);
         if (kmap) {
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) {
