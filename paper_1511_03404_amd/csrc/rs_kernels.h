@@ -59,7 +59,7 @@ struct PassCfg {
     static constexpr int kBallotWaves = THREADS / kWave / kBallotShare;
 };
 
-constexpr int kHistThreads = 256;
+constexpr int kHistThreads = 1024;
 
 struct Bufs {
     const void *in_k;
@@ -93,38 +93,32 @@ struct HistArgs {
     uint32_t kmap;        // key order (kMap*), applied to every key read
 };
 
-// Count one key's D digits into the wave's LDS sub-histograms.
-template <typename K, int R>
-__device__ __forceinline__ void count_one(uint32_t (*sh)[1 << R], K key)
+// Counters of k_hist: per digit position and per bin, kHistCols columns of
+// 32-bit counters, column = lane % kHistCols.  Only the kWave / kHistCols
+// lanes of a column can meet on one word, so a digit shared by the whole
+// wave (zero, sorted or reverse keys) serialises kWave / kHistCols ways, not
+// kWave; spread digits mostly land in different banks.
+constexpr int kHistCols = 16;
+
+template <int R>
+__device__ __forceinline__ void hist_add(uint32_t *tab, int p, uint32_t dg, uint32_t col)
 {
-    constexpr int D = num_passes<K, R>();
-#pragma unroll
-    for (int p = 0; p < D; ++p)
-        atomicAdd(&sh[p][digit_of<R>(key, p * R)], 1u);
+    atomicAdd(&tab[(((uint32_t)p << R) + dg) * kHistCols + col], 1u);
 }
 
-// Count a batch of NK keys per thread (a full batch: every lane active).
-// Key slot i of the wave covers 64 neighbouring vectors of the input, and in
-// skewed inputs (zero, sorted, reverse) a digit position is often the same
-// over the whole slot; same-address LDS atomics serialise (0.5 lanes/clock
-// against ~6 for spread addresses), so such a slot adds 64 once.
-template <typename K, int R, int NK>
-__device__ __forceinline__ void count_batch(uint32_t (*sh)[1 << R], const K (&key)[NK])
+// Adds the counters into hist ([d][2^R]).  Row r (position r >> R, bin
+// r % 2^R) is summed by one thread, which starts at column r so that
+// neighbouring threads read different banks.
+template <int D, int R>
+__device__ __forceinline__ void hist_flush(const uint32_t *tab, uint32_t *hist, uint32_t t)
 {
-    constexpr int D = num_passes<K, R>();
+    for (uint32_t r = t; r < (uint32_t)D << R; r += kHistThreads) {
+        uint32_t s = 0;
 #pragma unroll
-    for (int p = 0; p < D; ++p) {
-#pragma unroll
-        for (int i = 0; i < NK; ++i) {
-            const uint32_t dg = digit_of<R>(key[i], p * R);
-            const uint32_t first = __builtin_amdgcn_readfirstlane(dg);
-            if (__ballot(dg != first) == 0) {
-                if (lane_id() == 0)
-                    atomicAdd(&sh[p][first], (uint32_t)kWave);
-            } else {
-                atomicAdd(&sh[p][dg], 1u);
-            }
-        }
+        for (uint32_t c = 0; c < kHistCols; ++c)
+            s += tab[r * kHistCols + ((c + r) & (kHistCols - 1))];
+        if (s)
+            atomicAdd(&hist[r], s);
     }
 }
 
@@ -132,18 +126,17 @@ template <typename K, int R>
 __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
 {
     constexpr int D = num_passes<K, R>();
-    constexpr int NB = 1 << R;
-    constexpr int W = kHistThreads / kWave;
     constexpr int KPV = 16 / (int)sizeof(K);  // keys per 16-byte vector
     constexpr int VPT = 16 / KPV;             // vectors per thread per batch
     constexpr int NK = VPT * KPV;             // 16 keys per thread per batch
     constexpr uint32_t BATCH = kHistThreads * VPT;
-    __shared__ uint32_t sh[W][D][NB];
+    constexpr uint32_t TAB = (D << R) * kHistCols;
+    __shared__ uint32_t tab[TAB];
 
     const uint32_t t = threadIdx.x;
-    const uint32_t w = t / kWave;
-    for (int i = t; i < W * D * NB; i += kHistThreads)
-        (&sh[0][0][0])[i] = 0;
+    const uint32_t col = t % kHistCols;
+    for (uint32_t i = t; i < TAB; i += kHistThreads)
+        tab[i] = 0;
 
     // clear the look-back words of every pass
     const uint64_t gtid = (uint64_t)blockIdx.x * kHistThreads + t;
@@ -179,7 +172,12 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
             for (int i = 0; i < NK; ++i)
                 key[i] = map_in(key[i], a.kmap);
         }
-        count_batch<K, R, NK>(sh[w], key);
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+#pragma unroll
+            for (int i = 0; i < NK; ++i)
+                hist_add<R>(tab, p, digit_of<R>(key[i], p * R), col);
+        }
     }
     // the rest: unaligned head, vectors after the last full batch, ragged
     // tail -- element by element, spread over the whole grid
@@ -187,18 +185,13 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
     const uint64_t extra = a.head + (a.n - rest0);
     for (uint64_t i = gtid; i < extra; i += gstride) {
         const uint64_t idx = i < a.head ? i : rest0 + (i - a.head);
-        count_one<K, R>(sh[w], map_in(keys[idx], a.kmap));
+        const K key = map_in(keys[idx], a.kmap);
+#pragma unroll
+        for (int p = 0; p < D; ++p)
+            hist_add<R>(tab, p, digit_of<R>(key, p * R), col);
     }
     __syncthreads();
-
-    for (int i = t; i < D * NB; i += kHistThreads) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int ww = 0; ww < W; ++ww)
-            s += (&sh[ww][0][0])[i];
-        if (s)
-            atomicAdd(&a.hist[i], s);
-    }
+    hist_flush<D, R>(tab, a.hist, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,8 +681,8 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
 // ---------------------------------------------------------------------------
 // Segmented sort: digit histograms of the large segments, chunk by chunk.
 // Persistent workgroups claim chunks of kSegChunk elements, count all digit
-// positions in LDS and add the counts to the segment's histogram (global
-// atomics).
+// positions in the column table of k_hist and add the counts to the
+// segment's histogram (global atomics).
 
 struct SegHistArgs {
     const void *kin;
@@ -702,23 +695,28 @@ struct SegHistArgs {
     uint32_t kmap;       // key order applied to every key read
 };
 
+constexpr int kSegHistThreads = 1024;
+
 template <typename K, int R>
-__global__ __launch_bounds__(256) void k_seg_hist(SegHistArgs a)
+__global__ __launch_bounds__(kSegHistThreads) void k_seg_hist(SegHistArgs a)
 {
     constexpr int D = num_passes<K, R>();
     constexpr int NB = 1 << R;
-    constexpr int W = 256 / kWave;
-    __shared__ uint32_t sh[W][D][NB];
+    constexpr int NK = 16;  // keys per thread per round, all loaded before counting
+    constexpr uint32_t ROUND = kSegHistThreads * NK;
+    constexpr uint32_t TAB = (D << R) * kHistCols;
+    __shared__ uint32_t tab[TAB];
     __shared__ uint32_t s_item;
     const uint32_t t = threadIdx.x;
-    const uint32_t w = t / kWave;
+    const uint32_t col = t % kHistCols;
     const K *keys = (const K *)a.kin;
     const uint32_t chunks = min(a.ctrl[kSegChunks], a.max_chunks);
+    for (uint32_t i = t; i < TAB; i += kSegHistThreads)
+        tab[i] = 0;
     while (true) {
+        // the barrier also ends the previous chunk's flush in every thread
         if (t == 0)
             s_item = atomicAdd(&a.ctrl[kSegChunkClaim], 1u);
-        for (int i = t; i < W * D * NB; i += 256)
-            (&sh[0][0][0])[i] = 0;
         __syncthreads();
         const uint32_t item = s_item;
         if (item >= chunks)
@@ -733,34 +731,46 @@ __global__ __launch_bounds__(256) void k_seg_hist(SegHistArgs a)
         const uint64_t lo = (uint64_t)(item - first) * kSegChunk;
         const uint32_t len = rec.size > lo ? (uint32_t)min<uint64_t>(kSegChunk, rec.size - lo) : 0u;
         const K *sk = keys + rec.start + lo;
-        for (uint32_t i = t; i < len; i += 256) {
-            const K key = map_in(sk[i], a.kmap);
-            const uint64_t active = __ballot(1);  // before any branch narrows it
+        for (uint32_t r0 = 0; r0 < len; r0 += ROUND) {
+            if (r0 + ROUND <= len) {
+                K key[NK];
 #pragma unroll
-            for (int p = 0; p < D; ++p) {
-                const uint32_t dg = digit_of<R>(key, p * R);
-                // a digit held by the whole wave is added once (same-address
-                // LDS atomics serialise)
-                const uint32_t first_dg = __builtin_amdgcn_readfirstlane(dg);
-                if (__ballot(dg != first_dg) == 0) {
-                    if (lane_id() == (uint32_t)__builtin_ctzll(active))
-                        atomicAdd(&sh[w][p][first_dg], (uint32_t)__popcll(active));
-                } else {
-                    atomicAdd(&sh[w][p][dg], 1u);
+                for (int j = 0; j < NK; ++j)
+                    key[j] = sk[r0 + j * kSegHistThreads + t];
+                if (a.kmap) {
+#pragma unroll
+                    for (int j = 0; j < NK; ++j)
+                        key[j] = map_in(key[j], a.kmap);
+                }
+#pragma unroll
+                for (int p = 0; p < D; ++p) {
+#pragma unroll
+                    for (int j = 0; j < NK; ++j)
+                        hist_add<R>(tab, p, digit_of<R>(key[j], p * R), col);
+                }
+            } else {
+                for (uint32_t e = r0 + t; e < len; e += kSegHistThreads) {
+                    const K key = map_in(sk[e], a.kmap);
+#pragma unroll
+                    for (int p = 0; p < D; ++p)
+                        hist_add<R>(tab, p, digit_of<R>(key, p * R), col);
                 }
             }
         }
         __syncthreads();
+        // add the chunk's counts to its segment's histogram and clear them
         uint32_t *out = a.seg_hist + (uint64_t)seg * D * NB;
-        for (int i = t; i < D * NB; i += 256) {
-            uint32_t c = 0;
+        for (uint32_t r = t; r < (uint32_t)D << R; r += kSegHistThreads) {
+            uint32_t s = 0;
 #pragma unroll
-            for (int ww = 0; ww < W; ++ww)
-                c += (&sh[ww][0][0])[i];
-            if (c)
-                atomicAdd(&out[i], c);
+            for (uint32_t c = 0; c < kHistCols; ++c) {
+                const uint32_t i = r * kHistCols + ((c + r) & (kHistCols - 1));
+                s += tab[i];
+                tab[i] = 0;
+            }
+            if (s)
+                atomicAdd(&out[r], s);
         }
-        __syncthreads();
     }
 }
 

@@ -62,7 +62,7 @@ struct SegLaunch {
     using C = PassCfg<R, THREADS, ITEMS>;
     static void hist(const SegHistArgs &a, uint32_t grid, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_seg_hist<K, R>), dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_seg_hist<K, R>), dim3(grid), dim3(kSegHistThreads), 0, s, a);
     }
     static void scan(const SegHistArgs &a, uint32_t grid, hipStream_t s)
     {

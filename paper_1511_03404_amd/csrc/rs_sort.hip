@@ -480,7 +480,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     ha.status = (uint4 *)status;
     ha.status_vec = L.status_bytes / 16;
     const uint64_t hist_blocks = std::max<uint64_t>(
-        1, std::min<uint64_t>(2048, (n + 16383) / 16384));
+        1, std::min<uint64_t>(512, (n + 16383) / 16384));
     launch(ctx, s, sizeof(K) == 4 ? "k_hist_u32" : "k_hist_u64",
            [&] { op.hist(ha, (uint32_t)hist_blocks, s); });
 
@@ -808,7 +808,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     {
         SegHistArgs ha{kin, large, chunk_seg, (uint32_t)L.max_chunks, ctrl, seg_hist, seg_base,
                        kmap};
-        const uint32_t g = std::min<uint64_t>(grid_of(op.hist_kernel, 256), L.max_chunks);
+        const uint32_t g = std::min<uint64_t>(grid_of(op.hist_kernel, kSegHistThreads), L.max_chunks);
         launch(ctx, s, "k_seg_hist", [&] { op.hist(ha, g, s); });
         const uint32_t gs = std::min<uint32_t>(grid_of(op.scan_kernel, 256), nseg);
         launch(ctx, s, "k_seg_scan", [&] { op.scan(ha, gs, s); });
