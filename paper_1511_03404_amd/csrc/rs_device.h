@@ -5,9 +5,11 @@
 // element at its digit's running offset in input order.  On the GPU the
 // three steps are spread over a tile of T elements per workgroup:
 //   * count  -- a wave64 "multisplit": each lane learns the mask of lanes
-//               holding the same digit (from a per-wave LDS table of lane
-//               masks, or from one ballot per digit bit when the digits are
-//               skewed); the lowest such lane adds the group size to a
+//               holding the same digit (most waves from a per-wave LDS
+//               table of lane masks, the others, and every wave when the
+//               digits are skewed, from one ballot per digit bit, so the
+//               LDS and the VALU share the work); the lowest such lane adds
+//               the group size to a
 //               per-wave LDS counter, and the rank inside the group is mbcnt
 //               over the mask.  Items are visited in input order
 //               (wave-striped: item j of lane l is element j*64 + l of the

@@ -38,10 +38,11 @@ constexpr int kBallotShare = 4;
 // Configuration of the digit passes.
 //   kLookback  predecessor tiles read per look-back round trip
 //   kGroup     consecutive tiles claimed as a group (see claim_tile)
-// Keys are staged in LDS, written out, then the values go through the same
-// buffer; the per-wave lane-mask table is only live while ranking and shares
-// it too.  Big tiles amortise the per-tile latencies (tile claim, look-back)
-// and make the digit runs of the scatter longer.
+// Keys and values are staged in LDS in buffers of their own and written out
+// after one barrier; the per-wave lane-mask tables are only live while
+// ranking and share the key buffer.  Big tiles amortise the per-tile
+// latencies (tile claim, look-back) and make the digit runs of the scatter
+// longer.
 template <int R, int THREADS, int ITEMS>
 struct PassCfg {
     static_assert(R >= 4 && R <= 8, "digit widths of 4..8 bits");
@@ -219,8 +220,14 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
     __shared__ int s_skewed[D];
     __shared__ unsigned long long s_sq[kRadix / kWave];
     const uint32_t t = threadIdx.x;
+    // every row's load in flight at once, not one latency per digit position
+    uint32_t cnt[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+        cnt[p] = t < (uint32_t)NB ? a.hist[p * NB + t] : 0u;
+#pragma unroll
     for (int p = 0; p < D; ++p) {
-        const uint32_t c = t < (uint32_t)NB ? a.hist[p * NB + t] : 0u;
+        const uint32_t c = cnt[p];
         const uint32_t ex = bins_exclusive_scan<NB>(c, s_tmp);
         if (t < (uint32_t)NB)
             a.digit_base[p * NB + t] = ex;
