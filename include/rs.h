@@ -271,9 +271,9 @@ rs_status rs_config_get(rs_key_type key_type, int has_values, int index, rs_conf
  * kind whose size class ceil(log2 n) is size_log2 (0..39), or for every
  * size class if size_log2 is -1.  segmented != 0 selects the table of
  * rs_segmented_sort.  The built-in choice of a plain sort is the one the
- * autotuner selected on MI355X: 1024 x 8 tiles up to size class 21 (24 for
- * 64-bit pairs), 256 x 16 or 512 x 8 tiles at the smallest classes of some
- * kinds, index 0 above; segmented sorts use index 0.  Takes effect for
+ * autotuner selected on MI355X: 1024 x 8 tiles up to size class 21 (from
+ * class 18 up for 64-bit pairs), 256 x 16 or 512 x 8 tiles at the smallest
+ * classes of some kinds, index 0 above; segmented sorts use index 0.  Takes effect for
  * calls enqueued afterwards; a workspace sized before the change may be too
  * small for the new choice (the sort then returns RS_ERR_INVALID_ARGUMENT).
  */

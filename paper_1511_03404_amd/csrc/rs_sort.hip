@@ -143,7 +143,7 @@ static int default_index(int key_bytes, bool has_values, bool segmented, int c)
     if (key_bytes == 8 && has_values) {
         if (c <= 17)
             threads = 512, items = 8;
-        else if (c <= 24)
+        else
             threads = 1024, items = 8;
     } else if (c <= 15 && (has_values || key_bytes == 8)) {
         threads = 256, items = 16;

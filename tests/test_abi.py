@@ -148,7 +148,8 @@ def test_tune_table(rs, ctx):
     assert ctx.tune_get(32, True, False, 25) == 0
     assert ctx.tune_get(32, True, True, 26) == 0
     assert ctx.tune_get(32, False, False, 26) == 0
-    assert ctx.tune_get(64, True, False, 26) == 0
+    c64p = rs.configs(64, True)[ctx.tune_get(64, True, False, 26)]
+    assert (c64p["threads"], c64p["items"]) == (1024, 8)
     # smaller tiles: more look-back words in the workspace
     assert ctx.workspace_bytes(32, True, 1 << 26) > w0
     assert ctx.workspace_bytes(32, True, 1 << 25) == ctx.workspace_bytes(32, True, 1 << 25)
@@ -160,14 +161,15 @@ def test_tune_table(rs, ctx):
     assert ctx.tune_get(32, True, True, 17) == 0
     ctx.tune_set(32, True, False, 26, -1)
     # built-in choices of unset plain-sort classes: 1024 x 8 tiles up to 2^21
-    # (2^24 for 64-bit pairs), the list's default above
+    # (from 2^18 up for 64-bit pairs), the list's default above
     for bits, pairs in ((32, False), (32, True), (64, False), (64, True)):
         c = rs.configs(bits, pairs)
-        big = 24 if (bits, pairs) == (64, True) else 21
-        for cls in ((18, big) if (bits, pairs) == (64, True) else (17, big)):
+        big = 39 if (bits, pairs) == (64, True) else 21
+        for cls in ((18, 25, big) if (bits, pairs) == (64, True) else (17, big)):
             i = ctx.tune_get(bits, pairs, False, cls)
             assert (c[i]["threads"], c[i]["items"], c[i]["radix_bits"]) == (1024, 8, 8), (bits, pairs, cls)
-        assert ctx.tune_get(bits, pairs, False, big + 1 if big < 24 else 25) == 0
+        if big < 39:
+            assert ctx.tune_get(bits, pairs, False, big + 1) == 0
         assert ctx.tune_get(bits, pairs, True, 17) == 0
     assert ctx.workspace_bytes(32, True, 1 << 26) == w0
     L = rs.lib()
