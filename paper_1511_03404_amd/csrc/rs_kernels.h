@@ -20,6 +20,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cstddef>
 
 #include "rs_device.h"
 #include "rs_segmented.h"
@@ -38,11 +39,11 @@ constexpr int kBallotShare = 4;
 // Configuration of the digit passes.
 //   kLookback  predecessor tiles read per look-back round trip
 //   kGroup     consecutive tiles claimed as a group (see claim_tile)
-// Keys and values are staged in LDS in buffers of their own and written out
-// after one barrier; the per-wave lane-mask tables are only live while
-// ranking and share the key buffer.  Big tiles amortise the per-tile
-// latencies (tile claim, look-back) and make the digit runs of the scatter
-// longer.
+// The tile is staged in LDS in rank order (pairs as one (key, value) word
+// per element) and written out after one barrier; the per-wave lane-mask
+// tables are only live while ranking and share the staging memory.  Big
+// tiles amortise the per-tile latencies (tile claim, look-back) and make
+// the digit runs of the scatter longer.
 template <int R, int THREADS, int ITEMS>
 struct PassCfg {
     static_assert(R >= 4 && R <= 8, "digit widths of 4..8 bits");
@@ -457,10 +458,18 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
     }
 }
 
+// A staged (key, value) pair: one 8- or 16-byte LDS word.
+template <typename K>
+struct alignas(2 * sizeof(K)) KvPair {
+    K k;
+    K v;
+};
+
 // LDS of one digit pass: the per-wave counters, the digits' global bases and
-// the staging buffers of the keys (which hold the lane-mask tables while
-// ranking) and of the values, so both are staged in one step and written out
-// after one barrier.
+// the staging memory: a key buffer (which holds the lane-mask tables while
+// ranking) and a value buffer right after it, which pairs use as one array
+// of (key, value) words, staged in one step and written out after one
+// barrier.
 template <typename K, typename C, bool HAS_V>
 struct PassLds {
     static constexpr int W = C::kThreads / kWave;
@@ -499,6 +508,14 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
     static_assert(sizeof(V) == sizeof(K), "values have the key's width");
     K *s_k = (K *)L.stage;
     V *s_v = (V *)L.stage_v;
+    // pairs: one (key, value) word per element across both staging buffers,
+    // so staging is one LDS write per element at its rank and the writes
+    // read the pairs back in order
+    constexpr bool KV = HAS_V;
+    using Lds = PassLds<K, C, HAS_V>;
+    static_assert(!KV || offsetof(Lds, stage_v) == offsetof(Lds, stage) + Lds::kStageBytes,
+                  "the value buffer follows the key buffer");
+    KvPair<K> *s_kv = (KvPair<K> *)L.stage;
     uint64_t *s_mask = (uint64_t *)L.stage;
     const uint32_t t = threadIdx.x;
     const uint32_t w = t / kWave;
@@ -554,9 +571,13 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             rank[j] += wc[digit_of<R>(key[j], shift)];  // position in the tile
-            s_k[rank[j]] = key[j];
-            if constexpr (HAS_V)
-                s_v[rank[j]] = val[j];
+            if constexpr (KV) {
+                s_kv[rank[j]] = KvPair<K>{key[j], (K)val[j]};
+            } else {
+                s_k[rank[j]] = key[j];
+                if constexpr (HAS_V)
+                    s_v[rank[j]] = val[j];
+            }
         }
     }
     if (t < NB) {
@@ -600,9 +621,13 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             rank[j] += wc[digit_of<R>(key[j], shift)];
-            s_k[rank[j]] = key[j];
-            if constexpr (HAS_V)
-                s_v[rank[j]] = val[j];
+            if constexpr (KV) {
+                s_kv[rank[j]] = KvPair<K>{key[j], (K)val[j]};
+            } else {
+                s_k[rank[j]] = key[j];
+                if constexpr (HAS_V)
+                    s_v[rank[j]] = val[j];
+            }
         }
     }
     __syncthreads();
@@ -611,10 +636,18 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
     // place: write each digit run out with consecutive lanes on consecutive
     // addresses; then the values
     uint32_t dst[ITEMS];
+    V vk[KV ? ITEMS : 1];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t pos = i * THREADS + t;
-        const K k = s_k[pos];
+        K k;
+        if constexpr (KV) {
+            const KvPair<K> kv = s_kv[pos];
+            k = kv.k;
+            vk[i] = (V)kv.v;
+        } else {
+            k = s_k[pos];
+        }
         dst[i] = L.gbase[digit_of<R>(k, shift)] + pos;
         if (dst[i] < limit)
             store_at(dk, dst[i], map_out(k, map_store));
@@ -622,8 +655,12 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
     if constexpr (HAS_V) {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i)
-            if (dst[i] < limit)
-                store_at(dv, dst[i], s_v[i * THREADS + t]);
+            if (dst[i] < limit) {
+                if constexpr (KV)
+                    store_at(dv, dst[i], vk[i]);
+                else
+                    store_at(dv, dst[i], s_v[i * THREADS + t]);
+            }
     }
     __syncthreads();  // LDS is reused by the next tile
 }
