@@ -619,10 +619,10 @@ def bench_merge(args, torch, rs, datagen, dev):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(bits, has_v, dists, sample_log2, min_seconds=12.0, max_rounds=4):
+def cpu_baseline(bits, has_v, dists, sample_log2, min_seconds=12.0, max_repeats=4):
     """The oracle, as it stands, on a bounded sample of the same workload:
     one sort per distribution at n = 2^sample_log2 (single thread), the set
-    repeated until it has run for at least min_seconds (at most max_rounds
+    repeated until it has run for at least min_seconds (at most max_repeats
     times)."""
     import datagen
     import oracle
@@ -630,20 +630,20 @@ def cpu_baseline(bits, has_v, dists, sample_log2, min_seconds=12.0, max_rounds=4
     inputs = [(datagen.keys(d, n, bits, seed=1), datagen.values(n, bits) if has_v else None)
               for d in dists]
     total_t = 0.0
-    rounds = 0
-    while rounds < max_rounds and (rounds == 0 or total_t < min_seconds):
+    repeats = 0
+    while repeats < max_repeats and (repeats == 0 or total_t < min_seconds):
         for k, v in inputs:
             t0 = time.perf_counter()
             oracle.sort(k, v)
             total_t += time.perf_counter() - t0
-        rounds += 1
+        repeats += 1
     return {
-        "value": round(rounds * len(dists) * n / total_t / 1e6, 3),
+        "value": round(repeats * len(dists) * n / total_t / 1e6, 3),
         "unit": "Mkeys/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"one sort per distribution ({','.join(dists)}) at n=2^{sample_log2}, "
-                  f"{bits}-bit {'pairs' if has_v else 'keys'}, seed 1, {rounds} round(s); "
+                  f"{bits}-bit {'pairs' if has_v else 'keys'}, seed 1, {repeats} repeat(s); "
                   f"{total_t:.1f} s",
     }
 
