@@ -23,9 +23,11 @@
  *    and an output, or between keys and values, is RS_ERR_INVALID_ARGUMENT.
  *  - ws / ws_bytes: scratch memory of at least rs_workspace_bytes() bytes,
  *    256-byte aligned.  ws == NULL makes the context allocate and keep a
- *    scratch buffer of its own (grow-only, freed by rs_context_destroy);
- *    that mode calls hipMalloc and is therefore not usable under stream
- *    capture.
+ *    scratch buffer of its own, one per stream (grow-only; growing waits for
+ *    that stream; all are freed by rs_context_destroy), so calls on
+ *    different streams never share scratch.  That mode calls hipMalloc and
+ *    is therefore not usable under stream capture.  Calls that share one
+ *    caller workspace must be ordered (same stream, or synchronised).
  *  - stream is a hipStream_t (NULL = the device's null stream).  Calls are
  *    asynchronous: the output is valid once the stream has completed.
  *    Device faults surface at the caller's next synchronisation.
@@ -34,6 +36,10 @@
  *  - One sort handles n < 2^30 elements (RS_ERR_UNSUPPORTED above that).
  *  - Nothing is thrown across this interface.  rs_last_error() returns a
  *    thread-local description of the last failure.
+ *  - Errors found on the device (a segment too large for one sort, a wait
+ *    on another workgroup that reached its bound) are recorded in the
+ *    workspace and reported by rs_workspace_status() once the stream has
+ *    completed; the enqueueing call has already returned RS_OK.
  *  - A context may be used from one host thread at a time.
  */
 #ifndef RS_H
@@ -123,12 +129,33 @@ rs_status rs_sort_pairs_u64(rs_context *ctx, const uint64_t *keys_in, const uint
  * device: up to the tiny cap (rs_segmented_tiny_cap_set, 1024 by default) a
  * bitonic network per wave (Section 2.1), up to 16384 elements (8192 for
  * 64-bit pairs) a one-workgroup LDS radix sort, larger ones batched digit
- * passes (Section 2.6); every class gives the same stable sort.
+ * passes (Section 2.6); every class gives the same stable sort.  One
+ * segment must hold fewer than 2^30 elements; a larger one is left
+ * unsorted and reported by rs_workspace_status (RS_ERR_UNSUPPORTED).
  */
 rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *keys_in,
                             const void *vals_in, void *keys_out, void *vals_out,
                             const uint64_t *offsets, uint32_t num_segments, uint64_t total,
                             void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Device-side status of the last rs_sort_* / rs_sort / rs_segmented_sort*
+ * call (n >= 1) that used workspace `ws` (NULL: the context's own scratch
+ * of `stream`).  Synchronises `stream`, then reads the error word the
+ * kernels leave in the workspace's control block:
+ *   RS_OK                    the sort completed;
+ *   RS_ERR_UNSUPPORTED       a segment of 2^30 or more elements was left
+ *                            unsorted (one segment is one radix sort, whose
+ *                            look-back count field has 30 bits);
+ *   RS_ERR_INVALID_ARGUMENT  overlapping segment offsets needed more tiles
+ *                            than the workspace holds; some segments were
+ *                            left unsorted;
+ *   RS_ERR_DEVICE            the stream failed, or a wait on another
+ *                            workgroup (a tile claim or a look-back)
+ *                            reached its bound: the output is not valid.
+ * Not meaningful for rs_merge_sort workspaces (the merge sort never waits).
+ */
+rs_status rs_workspace_status(rs_context *ctx, const void *ws, void *stream);
 
 /* Scratch bytes for rs_segmented_sort on `total` elements in num_segments
  * segments, with the configuration the tune table selects for `total`.
@@ -284,6 +311,36 @@ rs_status rs_tune_set(rs_context *ctx, rs_key_type key_type, int has_values, int
  * entry, or the built-in choice where it is unset. */
 rs_status rs_tune_get(const rs_context *ctx, rs_key_type key_type, int has_values, int segmented,
                       int size_log2, int *index);
+
+/*
+ * Test entry points (for the library's own tests; a working caller needs
+ * neither).
+ *
+ * rs_debug_wait_set: every wait of a digit pass on another workgroup (tile
+ * claims, the decoupled look-back of Section 2.6's prefix sums spread over
+ * tiles) polls at most spin_limit times without progress before it records
+ * an error and lets the kernel finish (default 2^22 polls, several seconds).
+ * stall bit 1 makes every look-back, bit 2 every tile claim after the
+ * first, treat its predecessor as not yet published, so that each such wait
+ * reaches its bound and the give-up path runs with every kernel still
+ * exiting normally.  Applies to later calls on the context.
+ * spin_limit 0 or unknown stall bits -> RS_ERR_INVALID_ARGUMENT.
+ *
+ * rs_debug_sort_stages: the plain radix sort's kernels stage by stage, for
+ * per-kernel checks against the counting sort of Section 2.6.  Runs the
+ * histogram kernel, copies the digit histograms (u32[d][2^r] for the
+ * configuration the tune table selects, d = ceil(key bits / r)) to the
+ * DEVICE array hist_out unless it is NULL, then only the digit passes of
+ * positions [0, passes): keys_out/vals_out receive the state after those
+ * passes (the input stably sorted by its low passes*r bits; passes = 0
+ * copies the input).  Always takes the multi-kernel path, whatever n.
+ * Unsigned ascending order; otherwise as rs_sort.
+ */
+rs_status rs_debug_wait_set(rs_context *ctx, uint32_t spin_limit, uint32_t stall);
+rs_status rs_debug_sort_stages(rs_context *ctx, rs_key_type key_type, const void *keys_in,
+                               const void *vals_in, void *keys_out, void *vals_out, uint64_t n,
+                               int passes, uint32_t *hist_out, void *ws, size_t ws_bytes,
+                               void *stream);
 
 /* Static description of a status code. */
 const char *rs_status_string(rs_status status);

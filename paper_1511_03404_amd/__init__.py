@@ -48,6 +48,7 @@ EXPORTED = (
     "rs_config_count", "rs_config_get", "rs_tune_set", "rs_tune_get",
     "rs_sort", "rs_segmented_sort_order", "rs_merge_sort", "rs_merge_workspace_bytes",
     "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get",
+    "rs_workspace_status", "rs_debug_wait_set", "rs_debug_sort_stages",
 )
 
 
@@ -111,6 +112,9 @@ def lib():
             L.rs_merge_workspace_bytes.argtypes = [vp, ci, ci, u64, ctypes.POINTER(sz)]
             L.rs_segmented_tiny_cap_set.argtypes = [vp, u32]
             L.rs_segmented_tiny_cap_get.argtypes = [vp, ctypes.POINTER(u32)]
+            L.rs_workspace_status.argtypes = [vp, vp, vp]
+            L.rs_debug_wait_set.argtypes = [vp, u32, u32]
+            L.rs_debug_sort_stages.argtypes = [vp, ci, vp, vp, vp, vp, u64, ci, vp, vp, sz, vp]
             for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
                          "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
                          "rs_segmented_sort", "rs_segmented_workspace_bytes",
@@ -118,7 +122,8 @@ def lib():
                          "rs_profile_read", "rs_config_count", "rs_config_get",
                          "rs_tune_set", "rs_tune_get", "rs_sort", "rs_segmented_sort_order",
                          "rs_merge_sort", "rs_merge_workspace_bytes",
-                         "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get"):
+                         "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get",
+                         "rs_workspace_status", "rs_debug_wait_set", "rs_debug_sort_stages"):
                 getattr(L, name).restype = ci
             _lib = L
     return _lib
@@ -198,6 +203,24 @@ class Context:
         _check(lib().rs_tune_get(self.handle, kt, int(has_values), int(segmented),
                                  int(size_log2), ctypes.byref(out)))
         return out.value
+
+    # -- device-side errors ----------------------------------------------
+    def status(self, workspace: torch.Tensor | None = None) -> int:
+        """Device-side status of the last sort that used ``workspace`` (None:
+        the context's own scratch of the current stream): synchronises the
+        current stream and returns the rs status code (RS_OK = 0)."""
+        return lib().rs_workspace_status(self.handle, _ptr(workspace), _stream(self.device))
+
+    def check(self, workspace: torch.Tensor | None = None):
+        """Raise RSError if the last sort on ``workspace`` failed on the device
+        (a segment of 2^30 or more elements, or a wait that gave up)."""
+        _check(self.status(workspace))
+
+    def debug_wait_set(self, spin_limit: int, stall: int = 0):
+        """Test only: bound of the waits on other workgroups and the stall
+        bits (1: look-back, 2: tile claims) that force those waits to their
+        bound."""
+        _check(lib().rs_debug_wait_set(self.handle, int(spin_limit), int(stall)))
 
     # -- per-kernel timing (HIP events around each launch) ---------------
     def profile_enable(self, on: bool = True):
@@ -417,3 +440,30 @@ def merge_sort(keys: torch.Tensor, values: torch.Tensor | None = None,
                                    _ptr(keys_out), _ptr(values_out), n, _ptr(ws), ws.numel(),
                                    _stream(ctx.device)))
     return (keys_out, values_out) if has_v else keys_out
+
+
+def sort_stages(keys: torch.Tensor, values: torch.Tensor | None = None, passes: int = 0, *,
+                ctx: Context | None = None):
+    """Test only: the plain radix sort's kernels up to digit position
+    ``passes`` (rs_debug_sort_stages), with the configuration the tune table
+    selects.  Returns (the digit histograms as a device uint32 tensor
+    [d, 2^r], the keys after those passes, the values after them or None)."""
+    bits = key_bits(keys)
+    n = keys.numel()
+    _check_tensor(keys, "keys", bits, n)
+    has_v = values is not None
+    if has_v:
+        _check_tensor(values, "values", bits, n)
+    ctx = ctx or context(keys.device.index)
+    kt = RS_KEY_U32 if bits == 32 else RS_KEY_U64
+    cfg = configs(bits, has_v)[ctx.tune_get(bits, has_v, False, size_class(n))]
+    r = cfg["radix_bits"]
+    d = (bits + r - 1) // r
+    hist = torch.zeros((d, 1 << r), dtype=torch.uint32, device=keys.device)
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(values) if has_v else None
+    ws = _workspace(ctx, ctx.workspace_bytes(bits, has_v, n), keys.device)
+    _check(lib().rs_debug_sort_stages(ctx.handle, kt, _ptr(keys), _ptr(values), _ptr(ko),
+                                      _ptr(vo), n, int(passes), _ptr(hist), _ptr(ws), ws.numel(),
+                                      _stream(ctx.device)))
+    return hist, ko, vo

@@ -41,6 +41,9 @@ struct BlockArgs {
     uint32_t *claim;
     uint64_t n;
     uint32_t kmap;  // key order (kMap*): applied on load, undone on store
+    // single sort with a caller's workspace: its error word, cleared here so
+    // that a status query after this sort does not report an older one
+    uint32_t *err_clear;
 };
 
 template <typename K, typename V, bool HAS_V, int THREADS, int ITEMS>
@@ -69,6 +72,8 @@ __global__ __launch_bounds__(THREADS) void k_block_sort(BlockArgs a)
     const V *vin = (const V *)a.vin;
     K *kout = (K *)a.kout;
     V *vout = (V *)a.vout;
+    if (a.err_clear && blockIdx.x == 0 && t == 0)
+        *a.err_clear = 0;
 
     for (uint32_t iter = 0;; ++iter) {
         if (t == 0)

@@ -47,15 +47,36 @@ constexpr int kCtrlPlan = 16;        // [16, 32): plan word per pass
 constexpr int kCtrlFinal = 48;       // final copy: 0 none, 1 tmp -> out
 constexpr int kCtrlWords = 64;
 
+// Error word: the same index in the control block of the plain and of the
+// segmented sort, read back by the host after the stream completes.
+constexpr int kCtrlError = 56;
+constexpr uint32_t kErrSegTooLarge = 1u;  // a segment of 2^30 or more elements was skipped
+constexpr uint32_t kErrSegTiles = 2u;     // segments needed more tiles than the workspace holds
+constexpr uint32_t kErrWait = 4u;         // a wait on another workgroup gave up (bound reached)
+
+// Waits on other workgroups (tile claims, look-back) poll at most this many
+// times without progress, then record kErrWait and go on, so that a lost
+// tile ends the kernel with an error instead of a hang.  A poll is one
+// device-scope load plus a short sleep (about 1 us under load), so the
+// default bound is several seconds: far beyond any wait of a working sort.
+constexpr uint32_t kDefaultSpinLimit = 1u << 22;
+
+// Test-only stalls (never set by a working caller): the look-back or the
+// tile claim treats every predecessor as not yet published, so each wait
+// runs into its bound.
+constexpr uint32_t kStallLookback = 1u;
+constexpr uint32_t kStallClaim = 2u;
+
 // Plan word of one pass.
 constexpr uint32_t kPlanRun = 1u;          // the pass moves data
-constexpr uint32_t kPlanCopyIn = 2u;       // no pass runs: copy in -> out here
+constexpr uint32_t kPlanCopyIn = 2u;       // no pass runs: copy the keys in -> out here
 constexpr int kPlanSrcShift = 2;           // buffer id, 2 bits
 constexpr int kPlanDstShift = 4;           // buffer id, 2 bits
 constexpr uint32_t kBufIn = 0, kBufOut = 1, kBufTmp = 2;
 constexpr uint32_t kPlanBallot = 64u;      // skewed digit: rank with ballots, not the LDS table
 constexpr uint32_t kPlanFirst = 128u;      // the first moving pass (reads the input)
 constexpr uint32_t kPlanLast = 256u;       // the last moving pass, writing the output
+constexpr uint32_t kPlanCopyInV = 512u;    // no pass runs: copy the values in -> out here
 
 template <typename K>
 struct KeyTraits;

@@ -208,7 +208,9 @@ struct PlanArgs {
     uint32_t *digit_base;
     uint32_t *ctrl;
     uint32_t n;
-    int in_place;
+    int keys_in_place;  // keys_out == keys_in
+    int vals_in_place;  // vals_out == vals_in (pairs only)
+    int limit;          // digit positions [0, limit) are sorted (the whole key: d)
 };
 
 template <typename K, int R>
@@ -248,21 +250,26 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
                 tot += s_sq[i];
             // above 1/100 many lanes of a wave share a slot of the LDS lane-mask
             // table, whose same-address atomics serialise; ballots do not
-            s_skewed[p] = tot * 100ull > (unsigned long long)a.n * a.n;
+            // (n < 2^30, so n^2 fits 64 bits; tot <= n^2)
+            s_skewed[p] = tot > (unsigned long long)a.n * a.n / 100ull;
         }
         __syncthreads();
     }
     __syncthreads();
     if (t == 0) {
+        const int limit = a.limit < D ? a.limit : D;
         int q_total = 0;
-        for (int p = 0; p < D; ++p)
+        for (int p = 0; p < limit; ++p)
             q_total += !s_trivial[p];
-        const bool odd_in_place = a.in_place && (q_total & 1);
+        // in place if either array is: the first moving pass must not write
+        // its own input
+        const bool in_place = a.keys_in_place || a.vals_in_place;
+        const bool odd_in_place = in_place && (q_total & 1);
         int q = 0;
         uint32_t prev = kBufIn;
         for (int p = 0; p < D; ++p) {
             uint32_t plan = 0;
-            if (!s_trivial[p]) {
+            if (p < limit && !s_trivial[p]) {
                 uint32_t dst;
                 if (odd_in_place)
                     dst = (q & 1) ? kBufOut : kBufTmp;
@@ -276,8 +283,11 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
             }
             a.ctrl[kCtrlPlan + p] = plan;
         }
-        if (q_total == 0 && !a.in_place)
-            a.ctrl[kCtrlPlan + D - 1] = kPlanCopyIn;
+        // no pass moves data: the output is the input, so each array that is
+        // not sorted in place is copied by the last pass launched
+        if (q_total == 0)
+            a.ctrl[kCtrlPlan + (limit > 0 ? limit - 1 : 0)] =
+                (a.keys_in_place ? 0u : kPlanCopyIn) | (a.vals_in_place ? 0u : kPlanCopyInV);
         a.ctrl[kCtrlFinal] = odd_in_place ? 1u : 0u;
     }
 }
@@ -297,6 +307,9 @@ struct PassArgs {
     uint32_t num_tiles;
     uint32_t num_groups;
     uint32_t kmap;  // key order (kMap*), 0 = unsigned ascending
+    uint32_t *err;        // error word of the control block (kErrWait)
+    uint32_t spin_limit;  // polls without progress before a wait gives up
+    uint32_t stall;       // test-only kStall* bits; 0 in every working call
 };
 
 // Which compute die (XCD) this wave runs on, from the XCC_ID hardware register.
@@ -331,6 +344,10 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 //
 // claims layout: [0, 8) per-XCD claim counters, then [8 + x*G + j] the id+1
 // of group j of XCD x (0 = not yet published, kNoTile = no group left).
+//
+// Both waits are bounded: after a.spin_limit polls the claim records
+// kErrWait and returns kNoTile (an opener that gives up still publishes
+// kNoTile for its group, so nobody waits on it).
 template <int GROUP>
 __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
 {
@@ -350,9 +367,17 @@ __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
             if (i == 0) {
                 uint32_t prev = 1;
                 if (j > 0) {
+                    uint32_t spins = 0;
                     while ((prev = __hip_atomic_load(&list[j - 1], __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                                                     __HIP_MEMORY_SCOPE_AGENT)) == 0 ||
+                           (a.stall & kStallClaim)) {
+                        if (++spins > a.spin_limit) {
+                            atomicOr(a.err, kErrWait);
+                            prev = kNoTile;
+                            break;
+                        }
                         __builtin_amdgcn_s_sleep(1);
+                    }
                 }
                 if (prev == kNoTile) {
                     v = kNoTile;
@@ -362,9 +387,17 @@ __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
                 }
                 __hip_atomic_store(&list[j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
+                uint32_t spins = 0;
                 while ((v = __hip_atomic_load(&list[j], __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT)) == 0)
+                                              __HIP_MEMORY_SCOPE_AGENT)) == 0 ||
+                       (a.stall & kStallClaim)) {
+                    if (++spins > a.spin_limit) {
+                        atomicOr(a.err, kErrWait);
+                        v = kNoTile;
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(1);
+                }
             }
             if (v == kNoTile)
                 return kNoTile;
@@ -496,7 +529,8 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
                                           V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
                                           uint32_t first_tile, uint32_t *status, uint32_t dbase,
                                           int shift, bool ballot_rank, uint32_t map_load,
-                                          uint32_t map_store, Hook &&after_lookback)
+                                          uint32_t map_store, const PassArgs &wait,
+                                          Hook &&after_lookback)
 {
     constexpr int R = C::kRadixBits;
     constexpr uint32_t NB = C::kBins;
@@ -583,10 +617,13 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
     if (t < NB) {
         // decoupled look-back: read LBW predecessors per round trip, add
         // their counts in order up to the first inclusive one; on a tile
-        // that has not published yet, wait and re-read from there
+        // that has not published yet, wait and re-read from there (at most
+        // wait.spin_limit rounds without progress: then the error word
+        // records kErrWait and the tile goes on with the prefix it has)
         uint32_t prefix = 0;
         int64_t k = (int64_t)tile - 1;
         const int64_t lo = first_tile;
+        uint32_t spins = 0;
         while (k >= lo) {
             uint32_t st[LBW];
 #pragma unroll
@@ -597,20 +634,26 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
                             : kFlagInc;
             int used = 0;
             bool done = false;
+            if (!(wait.stall & kStallLookback)) {
 #pragma unroll
-            for (int i = 0; i < LBW; ++i) {
-                if (!done && used == i) {
-                    const uint32_t f = st[i] & kFlagMask;
-                    if (f != 0) {
-                        prefix += st[i] & kCountMask;
-                        done = f == kFlagInc;
-                        used = i + 1;
+                for (int i = 0; i < LBW; ++i) {
+                    if (!done && used == i) {
+                        const uint32_t f = st[i] & kFlagMask;
+                        if (f != 0) {
+                            prefix += st[i] & kCountMask;
+                            done = f == kFlagInc;
+                            used = i + 1;
+                        }
                     }
                 }
             }
             if (done)
                 break;
             k -= used;
+            if (used == 0 && ++spins > wait.spin_limit) {
+                atomicOr(wait.err, kErrWait);
+                break;
+            }
             if (used < LBW)
                 __builtin_amdgcn_s_sleep(1);
         }
@@ -675,16 +718,19 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
     const uint32_t t = threadIdx.x;
     const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
     if (!(plan & kPlanRun)) {
-        if (plan & kPlanCopyIn) {
-            // no pass moves data: copy in -> out
+        if (plan & (kPlanCopyIn | kPlanCopyInV)) {
+            // no pass moves data: copy in -> out (each array not sorted in place)
             for (uint64_t tl = blockIdx.x; tl < a.num_tiles; tl += gridDim.x) {
                 const uint64_t lo = tl * T;
                 const uint64_t hi = std::min<uint64_t>(lo + T, a.n);
-                copy_range(pick<const K>(a.b, kBufIn, false), pick<K>(a.b, kBufOut, false), lo,
-                           hi, t, THREADS);
-                if constexpr (HAS_V)
-                    copy_range(pick<const V>(a.b, kBufIn, true), pick<V>(a.b, kBufOut, true), lo,
-                               hi, t, THREADS);
+                if (plan & kPlanCopyIn)
+                    copy_range(pick<const K>(a.b, kBufIn, false), pick<K>(a.b, kBufOut, false),
+                               lo, hi, t, THREADS);
+                if constexpr (HAS_V) {
+                    if (plan & kPlanCopyInV)
+                        copy_range(pick<const V>(a.b, kBufIn, true), pick<V>(a.b, kBufOut, true),
+                                   lo, hi, t, THREADS);
+                }
             }
         }
         return;
@@ -715,7 +761,7 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
         pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile,
                                   0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0,
                                   (plan & kPlanFirst) ? a.kmap : 0u,
-                                  (plan & kPlanLast) ? a.kmap : 0u, [&](uint32_t tt) {
+                                  (plan & kPlanLast) ? a.kmap : 0u, a, [&](uint32_t tt) {
                                       if (tt == 0)
                                           L.tile = claim_tile<C::kGroup>(a, xcc);
                                   });
@@ -867,6 +913,8 @@ struct SegPassArgs {
     int d;
     uint32_t map_load;   // key order applied to the keys read (first pass)
     uint32_t map_store;  // key order undone on the keys written (last pass into the output)
+    uint32_t spin_limit;  // polls without progress before a wait gives up
+    uint32_t stall;       // test-only kStall* bits; 0 in every working call
 };
 
 template <typename K, typename V, bool HAS_V, typename C>
@@ -882,6 +930,9 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
     pa.claims = a.claims;
     pa.num_tiles = std::min(a.ctrl[kSegTiles], a.max_tiles);
     pa.num_groups = (pa.num_tiles + C::kGroup - 1) / C::kGroup;
+    pa.err = a.ctrl + kSegError;
+    pa.spin_limit = a.spin_limit;
+    pa.stall = a.stall;
     const uint32_t xcc = t == 0 ? xcc_id() : 0u;
     while (true) {
         if (t == 0)
@@ -902,7 +953,7 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
                                   (K *)a.dst_k + rec.start,
                                   HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
                                   tile, rec.tile_start, a.status, dbase, a.shift, false,
-                                  a.map_load, a.map_store, [](uint32_t) {});
+                                  a.map_load, a.map_store, pa, [](uint32_t) {});
     }
 }
 

@@ -33,7 +33,7 @@ constexpr int kSegTiles = 3;
 constexpr int kSegSmallClaim = 4;
 constexpr int kSegMediumClaim = 5;
 constexpr int kSegHistClaim = 6;
-constexpr int kSegError = 7;        // bit 0: a segment of 2^30+ elements; bit 1: tiles overflow
+constexpr int kSegError = kCtrlError;  // kErrSegTooLarge, kErrSegTiles, kErrWait
 constexpr int kSegTinyLen = 8;
 constexpr int kSegTinyClaim = 9;
 constexpr int kSegPassCounter = 32; // [32, 48): group counter per pass
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_seg_classify(SegClassifyArgs a)
         } else if (size <= a.medium_cap) {
             a.medium_list[atomicAdd(&a.ctrl[kSegMediumLen], 1u)] = SegRange{start, (uint32_t)size, 0};
         } else if (size >= RS_MAX_ELEMENTS) {
-            atomicOr(&a.ctrl[kSegError], 1u);
+            atomicOr(&a.ctrl[kSegError], kErrSegTooLarge);
         } else {
             const uint32_t idx = atomicAdd(&a.ctrl[kSegLargeLen], 1u);
             const uint32_t nt = (uint32_t)((size + a.tile - 1) / a.tile);
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_seg_classify(SegClassifyArgs a)
             // holds: such a segment keeps its tiles but sorts nothing
             const bool fits = (uint64_t)ts + nt <= a.max_tiles;
             if (!fits)
-                atomicOr(&a.ctrl[kSegError], 2u);
+                atomicOr(&a.ctrl[kSegError], kErrSegTiles);
             a.large[idx] = SegLarge{start, fits ? (uint32_t)size : 0u, ts};
             for (uint32_t i = 0; i < nt && ts + i < a.max_tiles; ++i)
                 a.tile_seg[ts + i] = idx;

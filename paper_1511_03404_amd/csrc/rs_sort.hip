@@ -88,10 +88,17 @@ struct ProfRecord {
     size_t ev;  // index of the first of two events in the pool
 };
 
+// Scratch the context allocates for calls made with ws == NULL: one buffer
+// per stream, so that sorts on different streams never share one.
+struct OwnWorkspace {
+    hipStream_t stream;
+    void *ptr;
+    size_t bytes;
+};
+
 struct rs_context {
     int device = 0;
-    void *own_ws = nullptr;
-    size_t own_ws_bytes = 0;
+    std::vector<OwnWorkspace> own;
     // per-kernel timing (rs_profile_*)
     bool prof = false;
     int prof_tag = 0;
@@ -104,6 +111,9 @@ struct rs_context {
     int8_t tune[2][2][2][kTuneClasses];
     // segments of 2 .. tiny_cap elements go to the bitonic network (0: none)
     uint32_t tiny_cap = kTinyMax;
+    // bound of the waits on other workgroups, and test-only stalls
+    uint32_t spin_limit = kDefaultSpinLimit;
+    uint32_t stall = 0;
     rs_context() { memset(tune, -1, sizeof tune); }
 };
 
@@ -321,29 +331,45 @@ static uint32_t ctx_cus(rs_context *ctx)
     return ctx->cus;
 }
 
-static rs_status get_workspace(rs_context *ctx, void *ws, size_t ws_bytes, uint64_t need,
+static OwnWorkspace *own_workspace(rs_context *ctx, hipStream_t s)
+{
+    for (OwnWorkspace &o : ctx->own)
+        if (o.stream == s)
+            return &o;
+    return nullptr;
+}
+
+// The caller's workspace, or the context's own one for this stream, grown
+// to `need` bytes.  An own buffer is only ever used by sorts on its stream,
+// so growing it waits for that stream alone before the old one is freed.
+static rs_status get_workspace(rs_context *ctx, void *ws, uint64_t need, hipStream_t s,
                                void **out)
 {
     if (ws) {
         *out = ws;
         return RS_OK;
     }
-    if (ctx->own_ws_bytes < need) {
-        if (ctx->own_ws) {
-            (void)hipFree(ctx->own_ws);
-            ctx->own_ws = nullptr;
-            ctx->own_ws_bytes = 0;
+    OwnWorkspace *o = own_workspace(ctx, s);
+    if (!o) {
+        ctx->own.push_back({s, nullptr, 0});
+        o = &ctx->own.back();
+    }
+    if (o->bytes < need) {
+        if (o->ptr) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(o->ptr);
+            o->ptr = nullptr;
+            o->bytes = 0;
         }
-        if (hipMalloc(&ctx->own_ws, need) != hipSuccess) {
+        if (hipMalloc(&o->ptr, need) != hipSuccess) {
             (void)hipGetLastError();
-            ctx->own_ws = nullptr;
+            o->ptr = nullptr;
             return fail(RS_ERR_OUT_OF_MEMORY, "could not allocate %llu bytes of scratch",
                         (unsigned long long)need);
         }
-        ctx->own_ws_bytes = need;
+        o->bytes = need;
     }
-    (void)ws_bytes;
-    *out = ctx->own_ws;
+    *out = o->ptr;
     return RS_OK;
 }
 
@@ -415,9 +441,14 @@ static const char *pass_name()
     return HAS_V ? "k_pass_u64_pairs" : "k_pass_u64_keys";
 }
 
+// limit >= 0 and hist_out are for the per-kernel test entry point only:
+// stop after `limit` digit positions (the state after that many passes lands
+// in the output), copy the digit histograms to hist_out, and always take the
+// multi-kernel path.
 template <typename K, bool HAS_V>
 static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, K *vout,
-                          uint64_t n, void *ws, size_t ws_bytes, void *stream, uint32_t kmap = 0)
+                          uint64_t n, void *ws, size_t ws_bytes, void *stream, uint32_t kmap = 0,
+                          int limit = -1, uint32_t *hist_out = nullptr)
 {
     if (!ctx)
         return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
@@ -432,9 +463,18 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
     hipStream_t s = (hipStream_t)stream;
     using B = BlockShape<K, HAS_V>;
-    if (n <= (uint64_t)B::kMediumCap) {
-        // the whole array fits one workgroup's LDS: one launch, all passes
-        BlockArgs ba{kin, vin, kout, vout, nullptr, nullptr, nullptr, n, kmap};
+    const bool debug = limit >= 0 || hist_out != nullptr;
+    if (n <= (uint64_t)B::kMediumCap && !debug) {
+        // the whole array fits one workgroup's LDS: one launch, all passes.
+        // The workspace is not needed; its error word is cleared.
+        uint32_t *err_clear = nullptr;
+        if (ws) {
+            err_clear = (uint32_t *)ws + kCtrlError;
+        } else if (OwnWorkspace *o = own_workspace(ctx, s)) {
+            if (o->ptr)
+                err_clear = (uint32_t *)o->ptr + kCtrlError;
+        }
+        BlockArgs ba{kin, vin, kout, vout, nullptr, nullptr, nullptr, n, kmap, err_clear};
         if (n <= (uint64_t)B::kSmallCap) {
             launch(ctx, s, "k_block_sort_small", [&] {
                 hipLaunchKernelGGL((k_block_sort<K, K, HAS_V, B::kSmallThreads, B::kItems>),
@@ -452,7 +492,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         return RS_OK;
     }
     void *w = nullptr;
-    st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
+    st = get_workspace(ctx, ws, L.total, (hipStream_t)stream, &w);
     if (st != RS_OK)
         return st;
     char *wb = (char *)w;
@@ -460,8 +500,12 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     uint32_t *hist = (uint32_t *)(wb + L.off_hist);
     uint32_t *base = (uint32_t *)(wb + L.off_base);
     uint32_t *status = (uint32_t *)(wb + L.off_status);
-    // in-place if either array is: the first moving pass must not write its own input
-    const bool in_place = (const void *)kin == (const void *)kout || (HAS_V && vin == vout);
+    // in place if either array is (the first moving pass must not write its
+    // own input); an array not sorted in place is copied when no pass moves
+    const bool keys_in_place = (const void *)kin == (const void *)kout;
+    const bool vals_in_place = !HAS_V || vin == vout;
+    const bool in_place = keys_in_place || (HAS_V && vals_in_place);
+    const int run_passes = limit >= 0 ? std::min(limit, L.d) : L.d;
 
     Bufs b{kin, vin, kout, vout, wb + L.off_tmp_k, HAS_V ? (void *)(wb + L.off_tmp_v) : nullptr};
 
@@ -483,8 +527,12 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         1, std::min<uint64_t>(512, (n + 16383) / 16384));
     launch(ctx, s, sizeof(K) == 4 ? "k_hist_u32" : "k_hist_u64",
            [&] { op.hist(ha, (uint32_t)hist_blocks, s); });
+    if (hist_out &&
+        hipMemcpyAsync(hist_out, hist, (size_t)L.d * L.bins * 4, hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+        return fail(RS_ERR_DEVICE, "histogram copy failed");
 
-    PlanArgs pl{hist, base, ctrl, (uint32_t)n, in_place};
+    PlanArgs pl{hist, base, ctrl, (uint32_t)n, keys_in_place, vals_in_place, run_passes};
     launch(ctx, s, "k_plan", [&] { op.plan(pl, s); });
 
     // workgroups loop over claimed tiles: launch only what fits on the device
@@ -495,7 +543,9 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     // and process them one after another.
     const uint32_t pass_grid = (uint32_t)std::min<uint64_t>(
         L.tiles * kXcdSlots, (uint64_t)resident_blocks(op.pass_kernel, op.threads) * ctx_cus(ctx));
-    for (int p = 0; p < L.d; ++p) {
+    // the passes of digit positions [0, run_passes); at least one is launched,
+    // which copies the input when no pass moves data
+    for (int p = 0; p < std::max(run_passes, 1); ++p) {
         PassArgs pa{};
         pa.b = b;
         pa.n = (uint32_t)n;
@@ -508,6 +558,9 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         pa.num_tiles = (uint32_t)L.tiles;
         pa.num_groups = (uint32_t)((L.tiles + kClaimGroup - 1) / kClaimGroup);
         pa.kmap = kmap;
+        pa.err = ctrl + kCtrlError;
+        pa.spin_limit = ctx->spin_limit;
+        pa.stall = ctx->stall;
         launch(ctx, s, pass_name<K, HAS_V>(), [&] { op.pass(pa, pass_grid, s); });
     }
     if (in_place) {
@@ -588,7 +641,7 @@ static rs_status run_merge(rs_context *ctx, const K *kin, const K *vin, K *kout,
     char *wb = nullptr;
     if (L.levels > 0) {
         void *w = nullptr;
-        st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
+        st = get_workspace(ctx, ws, L.total, (hipStream_t)stream, &w);
         if (st != RS_OK)
             return st;
         wb = (char *)w;
@@ -729,7 +782,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     if (!guard.ok)
         return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
     void *w = nullptr;
-    rs_status st = get_workspace(ctx, ws, ws_bytes, L.total, &w);
+    rs_status st = get_workspace(ctx, ws, L.total, (hipStream_t)stream, &w);
     if (st != RS_OK)
         return st;
     hipStream_t s = (hipStream_t)stream;
@@ -784,7 +837,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     }
     {
         BlockArgs ba{kin, vin, kout, vout, small_list, ctrl + kSegSmallLen, ctrl + kSegSmallClaim,
-                     0, kmap};
+                     0, kmap, nullptr};
         auto kern = k_block_sort<K, K, HAS_V, B::kSmallThreads, B::kItems>;
         const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, B::kSmallThreads), nseg);
         launch(ctx, s, "k_block_sort_small", [&] {
@@ -793,7 +846,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     }
     {
         BlockArgs ba{kin, vin, kout, vout, medium_list, ctrl + kSegMediumLen,
-                     ctrl + kSegMediumClaim, 0, kmap};
+                     ctrl + kSegMediumClaim, 0, kmap, nullptr};
         auto kern = k_block_sort<K, K, HAS_V, B::kMediumThreads, B::kItems>;
         const uint32_t g = std::min<uint32_t>(grid_of((const void *)kern, B::kMediumThreads), nseg);
         launch(ctx, s, "k_block_sort_medium", [&] {
@@ -837,6 +890,8 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
             pa.d = L.d;
             pa.map_load = p == 0 ? kmap : 0u;
             pa.map_store = (p == L.d - 1 && to_out) ? kmap : 0u;
+            pa.spin_limit = ctx->spin_limit;
+            pa.stall = ctx->stall;
             launch(ctx, s, sizeof(K) == 4 ? "k_seg_pass_u32" : "k_seg_pass_u64",
                    [&] { op.pass(pa, g, s); });
             src_k = pa.dst_k;
@@ -882,10 +937,11 @@ void rs_context_destroy(rs_context *ctx)
 {
     if (!ctx)
         return;
-    if (ctx->own_ws || !ctx->events.empty()) {
+    if (!ctx->own.empty() || !ctx->events.empty()) {
         DeviceGuard g(ctx->device);
-        if (ctx->own_ws)
-            (void)hipFree(ctx->own_ws);
+        for (OwnWorkspace &o : ctx->own)
+            if (o.ptr)
+                (void)hipFree(o.ptr);
         for (hipEvent_t e : ctx->events)
             (void)hipEventDestroy(e);
     }
@@ -1094,6 +1150,85 @@ rs_status rs_segmented_sort(rs_context *ctx, rs_key_type key_type, const void *k
                                               num_segments, total, ws, ws_bytes, stream);
     }
     return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+}
+
+rs_status rs_workspace_status(rs_context *ctx, const void *ws, void *stream)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (ws && ((uintptr_t)ws & 255))
+        return fail(RS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const void *w = ws;
+    if (!w) {
+        OwnWorkspace *o = own_workspace(ctx, s);
+        if (!o || !o->ptr)
+            return RS_OK;  // no sort with the context's own scratch ran on this stream
+        w = o->ptr;
+    }
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    uint32_t word = 0;
+    hipError_t e = hipMemcpyAsync(&word, (const uint32_t *)w + kCtrlError, sizeof word,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RS_ERR_DEVICE, "stream failed: %s", hipGetErrorString(e));
+    }
+    if (word & kErrWait)
+        return fail(RS_ERR_DEVICE, "a wait on another workgroup reached its bound; the output "
+                                   "is not valid");
+    if (word & kErrSegTiles)
+        return fail(RS_ERR_INVALID_ARGUMENT, "the segments need more tiles than the workspace "
+                                             "holds (overlapping offsets); some were not sorted");
+    if (word & kErrSegTooLarge)
+        return fail(RS_ERR_UNSUPPORTED, "a segment of 2^30 or more elements was left unsorted");
+    return RS_OK;
+}
+
+rs_status rs_debug_wait_set(rs_context *ctx, uint32_t spin_limit, uint32_t stall)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    if (spin_limit == 0)
+        return fail(RS_ERR_INVALID_ARGUMENT, "spin_limit must be at least 1");
+    if (stall & ~(kStallLookback | kStallClaim))
+        return fail(RS_ERR_INVALID_ARGUMENT, "unknown stall bits 0x%x", stall);
+    ctx->spin_limit = spin_limit;
+    ctx->stall = stall;
+    return RS_OK;
+}
+
+rs_status rs_debug_sort_stages(rs_context *ctx, rs_key_type key_type, const void *keys_in,
+                               const void *vals_in, void *keys_out, void *vals_out, uint64_t n,
+                               int passes, uint32_t *hist_out, void *ws, size_t ws_bytes,
+                               void *stream)
+{
+    if (key_type != RS_KEY_U32 && key_type != RS_KEY_U64)
+        return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+    if (passes < 0)
+        return fail(RS_ERR_INVALID_ARGUMENT, "passes must be >= 0");
+    if ((vals_in != nullptr) != (vals_out != nullptr))
+        return fail(RS_ERR_INVALID_ARGUMENT, "vals_in and vals_out must both be given or both NULL");
+    if (key_type == RS_KEY_U32) {
+        if (vals_in)
+            return run_sort<uint32_t, true>(ctx, (const uint32_t *)keys_in,
+                                            (const uint32_t *)vals_in, (uint32_t *)keys_out,
+                                            (uint32_t *)vals_out, n, ws, ws_bytes, stream, 0,
+                                            passes, hist_out);
+        return run_sort<uint32_t, false>(ctx, (const uint32_t *)keys_in, nullptr,
+                                         (uint32_t *)keys_out, nullptr, n, ws, ws_bytes, stream, 0,
+                                         passes, hist_out);
+    }
+    if (vals_in)
+        return run_sort<uint64_t, true>(ctx, (const uint64_t *)keys_in, (const uint64_t *)vals_in,
+                                        (uint64_t *)keys_out, (uint64_t *)vals_out, n, ws,
+                                        ws_bytes, stream, 0, passes, hist_out);
+    return run_sort<uint64_t, false>(ctx, (const uint64_t *)keys_in, nullptr, (uint64_t *)keys_out,
+                                     nullptr, n, ws, ws_bytes, stream, 0, passes, hist_out);
 }
 
 rs_status rs_merge_workspace_bytes(const rs_context *ctx, rs_key_type key_type, int has_values,

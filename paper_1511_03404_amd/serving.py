@@ -6,7 +6,9 @@ execution slots (HIP streams).  Whenever a slot is free it forms a batch:
 the oldest pending request fixes the key type, and further pending requests
 of that type join in arrival order while the batch stays under its element
 budget and the device-memory cap (every byte of input staging, output and
-scratch of the in-flight batches counts).  A batch is one segmented sort
+scratch of the in-flight batches counts; ``HipBackend`` sizes a batch with
+the library's own workspace formulas and caps admission by the device's
+free memory).  A batch is one segmented sort
 (``rs_segmented_sort``) or, for a single request, one plain sort; batches on
 different slots overlap on the device.  Requests that arrive while others
 run are admitted as soon as a slot and memory free up.
@@ -45,10 +47,17 @@ class Request:
         return (self.bits, self.has_values)
 
     def footprint(self) -> int:
-        """Device bytes the request occupies while in flight: staged input,
-        output and scratch copies of keys and values."""
-        per = (self.bits // 8) * (2 if self.has_values else 1)
-        return 3 * per * self.n
+        """Device bytes the request occupies while in flight, as a batch of
+        its own under the default estimate (staged input, output and scratch
+        copies of keys and values)."""
+        return default_batch_bytes(self.kind, 1, self.n)
+
+
+def default_batch_bytes(kind, num_requests: int, elems: int) -> int:
+    """Estimate of a batch's device bytes when the backend gives none: staged
+    input, output and one scratch copy of the keys and values."""
+    bits, has_values = kind
+    return 3 * (bits // 8) * (2 if has_values else 1) * elems
 
 
 @dataclasses.dataclass
@@ -70,11 +79,16 @@ class Scheduler:
     and the rest carry on."""
 
     def __init__(self, backend, mem_cap: int = 64 * GiB, slots: int = 4,
-                 max_batch_elems: int = 1 << 26, max_batch_requests: int = 256):
+                 max_batch_elems: int = 1 << 26, max_batch_requests: int = 256,
+                 batch_bytes: Optional[Callable[[tuple, int, int], int]] = None):
+        """batch_bytes(kind, number of requests, elements) gives the device
+        bytes a batch occupies while in flight (default: default_batch_bytes);
+        a backend passes its exact figure."""
         if slots < 1 or mem_cap <= 0:
             raise ValueError("need at least one slot and a positive memory cap")
         self.backend = backend
         self.mem_cap = mem_cap
+        self.batch_bytes = batch_bytes or default_batch_bytes
         self.slots = slots
         self.max_batch_elems = max_batch_elems
         self.max_batch_requests = max_batch_requests
@@ -94,7 +108,7 @@ class Scheduler:
         self._next_batch = 0
 
     def submit(self, req: Request, now: float):
-        if req.footprint() > self.mem_cap:
+        if self.batch_bytes(req.kind, 1, req.n) > self.mem_cap:
             # could never fit: refuse it instead of blocking the queue
             self.rejected.append(req)
             return False
@@ -118,7 +132,7 @@ class Scheduler:
     def _form_batch(self):
         q = self._head_queue()
         head = q[0][1]
-        if self.mem_used + head.footprint() > self.mem_cap:
+        if self.mem_used + self.batch_bytes(head.kind, 1, head.n) > self.mem_cap:
             return None
         # requests of a kind are served in arrival order: the first one of
         # the head's kind that does not fit closes the batch
@@ -126,13 +140,15 @@ class Scheduler:
         while q:
             r = q[0][1]
             if not (len(chosen) < self.max_batch_requests
-                    and (not chosen or elems + r.n <= self.max_batch_elems)
-                    and self.mem_used + nbytes + r.footprint() <= self.mem_cap):
+                    and (not chosen or elems + r.n <= self.max_batch_elems)):
+                break
+            grown = self.batch_bytes(head.kind, len(chosen) + 1, elems + r.n)
+            if self.mem_used + grown > self.mem_cap:
                 break
             q.popleft()
             chosen.append(r)
             elems += r.n
-            nbytes += r.footprint()
+            nbytes = grown
         b = Batch(self._next_batch, self.free_slots.pop(), chosen, bytes=nbytes)
         self._next_batch += 1
         return b
@@ -267,6 +283,23 @@ class HipBackend:
         self.t0_event.record()
         self.t0_wall = None
 
+    def batch_bytes(self, kind, num_requests: int, elems: int) -> int:
+        """Device bytes of a batch while in flight, from the library's own
+        workspace formulas: the output, the staged inputs and offsets of a
+        multi-request batch, and the sort's workspace."""
+        bits, has_v = kind
+        data = elems * (bits // 8) * (2 if has_v else 1)
+        if num_requests <= 1:
+            return data + self.ctx.workspace_bytes(bits, has_v, elems)
+        return (2 * data + 8 * (num_requests + 1)
+                + self.ctx.segmented_workspace_bytes(bits, has_v, elems, num_requests))
+
+    def admission_cap(self, cap: int = 64 * GiB, reserve: int = 2 * GiB) -> int:
+        """The admission cap: ``cap``, or the device's free memory less
+        ``reserve`` when that is smaller."""
+        free, _ = self.torch.cuda.mem_get_info(self.dev)
+        return max(1, min(cap, free - reserve))
+
     def mark_clock_zero(self, wall_now: float):
         """Tie GPU event times to the serving clock: event 0 <-> wall_now."""
         torch = self.torch
@@ -282,6 +315,14 @@ class HipBackend:
         bits, has_v = reqs[0].kind
         dt = torch.uint32 if bits == 32 else torch.uint64
         total = sum(r.n for r in reqs)
+        # the payloads may still be in production on the caller's stream:
+        # the slot's stream waits for it, and the caching allocator keeps
+        # their memory for the slot's stream until it has used them
+        s.wait_stream(torch.cuda.current_stream(self.dev))
+        for r in reqs:
+            for t in r.payload:
+                if t is not None:
+                    t.record_stream(s)
         with torch.cuda.stream(s):
             if len(reqs) == 1:
                 k, v = reqs[0].payload

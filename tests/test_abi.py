@@ -266,3 +266,28 @@ def test_tiny_cap_setting(rs, ctx):
     assert L.rs_segmented_tiny_cap_set(ctx.handle, 1025) == rs.RS_ERR_INVALID_ARGUMENT
     assert L.rs_segmented_tiny_cap_set(None, 8) == rs.RS_ERR_INVALID_ARGUMENT
     assert ctx.tiny_cap() == 777
+
+
+def test_status_query_and_test_entry_points_validate_on_the_host(rs, ctx):
+    """The device-status query and the test entry points reject bad
+    arguments before any HIP call; a status query with no sort run on the
+    context's own scratch is RS_OK without touching the device."""
+    L = rs.lib()
+    fake = 0x7F0000000000
+    assert L.rs_workspace_status(None, None, None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_workspace_status(ctx.handle, fake + 16, None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"aligned" in L.rs_last_error()
+    assert L.rs_workspace_status(ctx.handle, None, None) == rs.RS_OK
+    assert L.rs_debug_wait_set(ctx.handle, 0, 0) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_debug_wait_set(ctx.handle, 16, 4) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"stall" in L.rs_last_error()
+    assert L.rs_debug_wait_set(ctx.handle, 16, 3) == rs.RS_OK
+    assert L.rs_debug_wait_set(ctx.handle, 1 << 22, 0) == rs.RS_OK
+    st = L.rs_debug_sort_stages
+    assert st(ctx.handle, 0, fake, None, fake + (1 << 20), None, 100, -1, None, None, 0,
+              None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert st(ctx.handle, 7, fake, None, fake + (1 << 20), None, 100, 1, None, None, 0,
+              None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert st(ctx.handle, 0, fake, fake + (1 << 21), fake + (1 << 20), None, 100, 1, None, None,
+              0, None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert st(ctx.handle, 0, None, None, None, None, 0, 2, None, None, 0, None) == rs.RS_OK

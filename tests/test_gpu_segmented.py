@@ -155,3 +155,60 @@ def test_repeatable_with_caller_workspace(rs):
         outs.append((ko.cpu().numpy(), vo.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     assert certify_segmented(keys, outs[0][0], outs[0][1], off) is None
+
+
+def certify_segmented_on_device(kin, kout, vout, offd, chunk=1 << 26):
+    """The segmented certificate, computed on the device chunk by chunk
+    (with value = index within the segment): every value lies in its
+    segment, its input key equals the output key, and inside a segment the
+    (key, value) pairs strictly increase.  Together these make each
+    segment's values a permutation and its output the unique stable sort."""
+    total = kin.numel()
+    u = 0xFFFFFFFF
+    for lo in range(0, total, chunk):
+        hi = min(total, lo + chunk + 1)  # one element of overlap for the pairwise test
+        idx = torch.arange(lo, hi, dtype=torch.int64, device="cuda")
+        seg = torch.searchsorted(offd, idx, right=True) - 1
+        start = offd[seg]
+        size = offd[seg + 1] - start
+        k = kout[lo:hi].to(torch.int64) & u
+        v = vout[lo:hi].to(torch.int64) & u
+        assert bool((v < size).all()), f"value outside its segment near {lo}"
+        assert bool(((kin[start + v].to(torch.int64) & u) == k).all()), \
+            f"key/value mismatch near {lo}"
+        same = seg[1:] == seg[:-1]
+        dk = k[1:] - k[:-1]
+        dv = v[1:] - v[:-1]
+        ok = (dk > 0) | ((dk == 0) & (dv > 0))
+        assert bool((ok | ~same).all()), f"order broken inside a segment near {lo}"
+
+
+def test_full_batch_20000_segments(rs, oracle_lib):
+    """The batched workload at full size: 20,000 segments with log-uniform
+    sizes in [16, 2^20] (about 1.9e9 pairs), uniform u32 keys, value = index
+    within the segment.  Certified on the device on every element; a sample
+    of segments (the largest, the smallest and random ones) against the
+    oracle."""
+    keys, vals, off = datagen.segmented(num_segments=20000, bits=32, seed=1)
+    total = int(off[-1])
+    print(f"case full segmented batch: 20000 segments, {total} pairs", flush=True)
+    kd = torch.from_numpy(keys).cuda()
+    vd = torch.from_numpy(vals).cuda()
+    offd = torch.from_numpy(off.view(np.int64)).cuda()
+    ctx = rs.context(0)
+    ws = torch.empty(ctx.segmented_workspace_bytes(32, True, total, 20000), dtype=torch.uint8,
+                     device="cuda")
+    ko, vo = rs.segmented_sort(kd, vd, offd, ctx=ctx, workspace=ws)
+    assert ctx.status(ws) == rs.RS_OK
+    del ws
+    certify_segmented_on_device(kd.view(torch.int32), ko.view(torch.int32), vo.view(torch.int32),
+                                offd)
+    sizes = np.diff(off.astype(np.int64))
+    rng = np.random.RandomState(1)
+    sample = set(rng.choice(20000, size=24, replace=False).tolist())
+    sample |= {int(np.argmax(sizes)), int(np.argmin(sizes))}
+    for s in sorted(sample):
+        a, b = int(off[s]), int(off[s + 1])
+        ok, ov = oracle_lib.sort(keys[a:b], vals[a:b])
+        assert np.array_equal(ko[a:b].cpu().numpy(), ok), f"segment {s}"
+        assert np.array_equal(vo[a:b].cpu().numpy(), ov), f"segment {s}"

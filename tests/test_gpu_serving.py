@@ -1,7 +1,9 @@
 """Serving loop on the GPU: requests of mixed sizes and key types, batched
 with each other into segmented sorts and overlapped on several streams,
-must each get exactly the result they get when sorted alone (tolerance 0:
-integer sorts are bit-exact)."""
+must each get exactly the result they get when sorted alone and the
+oracle's result (tolerance 0: integer sorts are bit-exact)."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -20,57 +22,117 @@ def rs():
     return rs
 
 
-def make(num, seed, hi_log2=18, rate_per_s=2000.0):
+def make(num, seed, hi_log2=18, rate_per_s=2000.0, pool_log2=20, fixed=(), fresh=False):
+    """Requests of the serving workload's law (log-uniform sizes from 2^10 to
+    2^hi_log2, key width and values by coin flips), keys sliced from one
+    resident random pool, values = index.  `fixed` appends requests of the
+    given (n, bits, has_values).  fresh=True makes every payload a new tensor
+    computed on the current stream (not yet complete when serving starts)."""
     from paper_1511_03404_amd.serving import Request
-    pool = torch.from_numpy(datagen.MT19937(seed).u64(1 << 20)).cuda()
-    idx32 = torch.arange(1 << hi_log2, dtype=torch.int64, device="cuda").to(torch.uint32)
-    idx64 = torch.arange(1 << hi_log2, dtype=torch.int64, device="cuda").to(torch.uint64)
+    pool = torch.from_numpy(datagen.MT19937(seed).u64(1 << pool_log2)).cuda()
+    top = max([1 << hi_log2] + [f[0] for f in fixed])
+    idx32 = torch.arange(top, dtype=torch.int64, device="cuda").to(torch.uint32)
+    idx64 = torch.arange(top, dtype=torch.int64, device="cuda").to(torch.uint64)
+    qs = list(datagen.requests(num, rate_per_s=rate_per_s, lo_log2=10, hi_log2=hi_log2,
+                               seed=seed))
+    last = qs[-1]["arrival_s"] if qs else 0.0
+    for i, (n, bits, hv) in enumerate(fixed):
+        qs.append({"id": len(qs), "n": n, "bits": bits, "has_values": hv,
+                   "arrival_s": last + 1e-6 * (i + 1), "key_seed": 7919 * (i + 1)})
     reqs = []
-    for q in datagen.requests(num, rate_per_s=rate_per_s, lo_log2=10, hi_log2=hi_log2, seed=seed):
+    for q in qs:
         n, bits = q["n"], q["bits"]
-        if bits == 32:
-            src = pool.view(torch.uint32)
-        else:
-            src = pool
+        src = pool.view(torch.uint32) if bits == 32 else pool
         off = q["key_seed"] % (src.numel() - n)
         keys = src[off:off + n]
+        if fresh:
+            keys = keys.clone()
         vals = (idx32 if bits == 32 else idx64)[:n] if q["has_values"] else None
         reqs.append(Request(q["id"], n, bits, q["has_values"], q["arrival_s"],
                             payload=(keys, vals)))
     return reqs
 
 
-@pytest.mark.parametrize("open_loop", [False, True])
-def test_each_result_same_alone_and_in_the_mix(rs, open_loop):
-    import time
+def run(rs, reqs, open_loop, slots=3, cap=1 << 30, max_elems=1 << 19, max_reqs=16):
     from paper_1511_03404_amd.serving import HipBackend, Scheduler, serve
+    be = HipBackend(slots=slots, max_batch_requests=max_reqs)
+    sch = Scheduler(be, mem_cap=be.admission_cap(cap), slots=slots, max_batch_elems=max_elems,
+                    max_batch_requests=max_reqs, batch_bytes=be.batch_bytes)
+    t0 = time.perf_counter()
+    be.mark_clock_zero(0.0)
+    return sch, serve(sch, reqs, lambda: time.perf_counter() - t0, open_loop=open_loop)
+
+
+def check_each(rs, oracle_lib, done):
+    """Every result equals the same request sorted alone and the oracle's
+    sort of its keys (pairs also pass the exact stable-sort certificate)."""
+    for r in done:
+        keys, vals = r.payload
+        kin = keys.cpu().numpy()
+        if vals is None:
+            alone = rs.sort_keys(keys)
+            torch.cuda.synchronize()
+            assert torch.equal(r.result[0], alone), f"request {r.id}"
+            ok, _ = oracle_lib.sort(kin)
+            assert np.array_equal(r.result[0].cpu().numpy(), ok), f"request {r.id} vs oracle"
+        else:
+            ak, av = rs.sort_pairs(keys, vals)
+            torch.cuda.synchronize()
+            assert torch.equal(r.result[0], ak) and torch.equal(r.result[1], av), \
+                f"request {r.id}"
+            gk, gv = r.result[0].cpu().numpy(), r.result[1].cpu().numpy()
+            ok, ov = oracle_lib.sort(kin, vals.cpu().numpy())
+            assert np.array_equal(gk, ok) and np.array_equal(gv, ov), f"request {r.id} vs oracle"
+            assert certify_stable_sort(kin, gk, gv) is None
+        assert r.done_s >= r.arrival_s
+
+
+@pytest.mark.parametrize("open_loop", [False, True])
+def test_each_result_same_alone_and_in_the_mix(rs, oracle_lib, open_loop):
     # open loop: 120 arrivals within about 120 us, faster than three slots
     # drain them, so later arrivals queue and share batches whatever the
     # speed of the sort (at a rate the GPU keeps up with, nothing would queue)
     reqs = make(120, seed=3, rate_per_s=1e6 if open_loop else 2000.0)
-    be = HipBackend(slots=3, max_batch_requests=16)
-    sch = Scheduler(be, mem_cap=1 << 30, slots=3, max_batch_elems=1 << 19,
-                    max_batch_requests=16)
-    t0 = time.perf_counter()
-    be.mark_clock_zero(0.0)
-    done = serve(sch, reqs, lambda: time.perf_counter() - t0, open_loop=open_loop)
+    sch, done = run(rs, reqs, open_loop)
     torch.cuda.synchronize()
     assert len(done) == 120 and not sch.failed and not sch.rejected
     sizes = [len([r for r in done if r.batch_id == b]) for b in {r.batch_id for r in done}]
     assert max(sizes) > 1, "no request was batched with another"
     if not open_loop:
         assert sch.peak_inflight > 1, "batches never overlapped"
-    for r in done:
-        keys, vals = r.payload
-        if vals is None:
-            alone = rs.sort_keys(keys)
-            torch.cuda.synchronize()
-            assert torch.equal(r.result[0], alone), f"request {r.id}"
-        else:
-            ak, av = rs.sort_pairs(keys, vals)
-            torch.cuda.synchronize()
-            assert torch.equal(r.result[0], ak) and torch.equal(r.result[1], av), f"request {r.id}"
-            kin = keys.cpu().numpy()
-            assert certify_stable_sort(kin, r.result[0].cpu().numpy(),
-                                       r.result[1].cpu().numpy()) is None
-        assert r.done_s >= r.arrival_s
+    check_each(rs, oracle_lib, done)
+
+
+def test_large_requests_of_both_widths(rs, oracle_lib):
+    """The workload's full size range, 2^10 .. 2^24 keys, with requests of
+    exactly 2^24 keys of each kind; a 1 GiB cap makes large requests queue
+    for memory while small ones batch."""
+    fixed = [(1 << 24, 32, False), (1 << 24, 32, True), (1 << 24, 64, False),
+             (1 << 24, 64, True)]
+    reqs = make(36, seed=5, hi_log2=24, rate_per_s=1e5, pool_log2=25, fixed=fixed)
+    print(f"case large requests: {len(reqs)} requests, {sum(r.n for r in reqs)} keys",
+          flush=True)
+    sch, done = run(rs, reqs, open_loop=True, slots=4, cap=1 << 30, max_elems=1 << 22)
+    torch.cuda.synchronize()
+    assert len(done) == len(reqs) and not sch.failed and not sch.rejected
+    assert {(r.bits, r.has_values) for r in done if r.n == 1 << 24} == \
+        {(32, False), (32, True), (64, False), (64, True)}
+    assert sch.peak_mem <= sch.mem_cap
+    check_each(rs, oracle_lib, done)
+
+
+def test_payloads_still_in_production_when_serving_starts(rs, oracle_lib):
+    """Payloads are new tensors computed on the default stream right before
+    serving starts, with no synchronisation: each slot's stream waits for
+    the caller's stream, so every result is still exact."""
+    from paper_1511_03404_amd.serving import HipBackend, Scheduler, serve
+    be = HipBackend(slots=3, max_batch_requests=16)
+    sch = Scheduler(be, mem_cap=be.admission_cap(1 << 30), slots=3, max_batch_elems=1 << 19,
+                    max_batch_requests=16, batch_bytes=be.batch_bytes)
+    t0 = time.perf_counter()
+    be.mark_clock_zero(0.0)
+    reqs = make(60, seed=9, rate_per_s=1e6, fresh=True)  # enqueued after the clock's sync
+    done = serve(sch, reqs, lambda: time.perf_counter() - t0, open_loop=True)
+    torch.cuda.synchronize()
+    assert len(done) == 60 and not sch.failed
+    check_each(rs, oracle_lib, done)

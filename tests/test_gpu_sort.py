@@ -189,3 +189,53 @@ def test_caller_workspace_and_streams(rs, oracle_lib):
             s.synchronize()
             ok, ov = oracle_lib.sort(keys, vals)
             assert np.array_equal(host(ko), ok) and np.array_equal(host(vo), ov)
+
+
+@pytest.mark.parametrize("n", [3000, 3 * TILE + 5])
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("mask_bits", [0, 8, 16, 24, None])
+@pytest.mark.parametrize("aliased", ["keys", "values"])
+def test_mixed_in_place_pairs(rs, oracle_lib, n, bits, mask_bits, aliased):
+    """Only one of the two arrays sorted in place: keys_out is keys_in with a
+    separate values_out, or the reverse.  With every pass skipped (mask 0)
+    the array that is not in place must still receive the input; with odd
+    and even numbers of moving passes the result lands in the same place."""
+    print(f"case mixed in-place n={n} bits={bits} mask={mask_bits} aliased={aliased}",
+          flush=True)
+    keys = datagen.keys("uniform", n, bits, seed=9)
+    if mask_bits is not None:
+        keys = keys & keys.dtype.type((1 << mask_bits) - 1)
+    vals = datagen.values(n, bits)
+    ok, ov = oracle_lib.sort(keys, vals)
+    kd, vd = dev(keys), dev(vals)
+    if aliased == "keys":
+        vo = torch.full_like(vd, 7)
+        ko, vo = rs.sort_pairs(kd, vd, kd, vo)
+    else:
+        ko = torch.full_like(kd, 7)
+        ko, vo = rs.sort_pairs(kd, vd, ko, vd)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ko), ok) and np.array_equal(host(vo), ov)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_device_status_is_ok_after_a_sort(rs, bits, pairs):
+    """The status query reads RS_OK after working sorts, small and large, with
+    a caller workspace and with the context's own scratch."""
+    ctx = rs.context(0)
+    for n in (1000, 3 * TILE + 5):
+        keys = dev(datagen.keys("uniform", n, bits, seed=n))
+        vals = dev(datagen.values(n, bits)) if pairs else None
+        ws = torch.empty(ctx.workspace_bytes(bits, pairs, n), dtype=torch.uint8, device="cuda")
+        if pairs:
+            rs.sort_pairs(keys, vals, workspace=ws)
+        else:
+            rs.sort_keys(keys, workspace=ws)
+        assert ctx.status(ws) == rs.RS_OK
+        f = rs.lib().rs_sort_pairs_u32 if bits == 32 else rs.lib().rs_sort_pairs_u64
+        if pairs:
+            ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+            rs._check(f(ctx.handle, rs._ptr(keys), rs._ptr(vals), rs._ptr(ko), rs._ptr(vo), n,
+                        None, 0, rs._stream(0)))
+            assert ctx.status(None) == rs.RS_OK

@@ -177,3 +177,30 @@ def test_forming_a_batch_does_not_scan_the_whole_queue():
     for r in done:
         batches.setdefault(r.batch_id, set()).add(r.kind)
     assert all(len(k) == 1 for k in batches.values())
+
+
+def test_admission_uses_the_backend_batch_size():
+    """A backend's batch size (here: a fixed workspace per batch plus a
+    per-request term, not additive over requests) decides admission: the
+    bytes held in flight never exceed the cap, and every batch's recorded
+    bytes are the function's value for that batch."""
+    calls = []
+
+    def batch_bytes(kind, nreq, elems):
+        calls.append((kind, nreq, elems))
+        return (1 << 20) + 4096 * nreq + 12 * elems
+
+    reqs = make_requests(150, seed=4)
+    be = FakeBackend(delay=3)
+    cap = 5 << 20
+    sch = Scheduler(be, mem_cap=cap, slots=3, max_batch_elems=1 << 16,
+                    batch_bytes=batch_bytes)
+    done = serve(sch, reqs, Clock(), open_loop=False, sleep=lambda s: None)
+    assert len(done) == 150 and not sch.rejected and calls
+    assert sch.peak_mem <= cap
+    for b in be.launched:
+        assert b.bytes == batch_bytes(b.requests[0].kind, len(b.requests),
+                                      sum(r.n for r in b.requests))
+    # a request whose own batch could never fit is rejected, not queued
+    sch2 = Scheduler(FakeBackend(), mem_cap=1 << 20, slots=1, batch_bytes=batch_bytes)
+    assert not sch2.submit(reqs[0], 0.0) and sch2.rejected == [reqs[0]]
