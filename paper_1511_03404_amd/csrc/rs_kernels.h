@@ -209,7 +209,7 @@ struct PlanArgs {
     uint32_t *ctrl;
     uint32_t n;
     int keys_in_place;  // keys_out == keys_in
-    int vals_in_place;  // vals_out == vals_in (pairs only)
+    int vals_in_place;  // pairs with vals_out == vals_in (0 for keys only)
     int limit;          // digit positions [0, limit) are sorted (the whole key: d)
 };
 

@@ -503,8 +503,8 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     // in place if either array is (the first moving pass must not write its
     // own input); an array not sorted in place is copied when no pass moves
     const bool keys_in_place = (const void *)kin == (const void *)kout;
-    const bool vals_in_place = !HAS_V || vin == vout;
-    const bool in_place = keys_in_place || (HAS_V && vals_in_place);
+    const bool vals_in_place = HAS_V && vin == vout;  // keys only: no values to place
+    const bool in_place = keys_in_place || vals_in_place;
     const int run_passes = limit >= 0 ? std::min(limit, L.d) : L.d;
 
     Bufs b{kin, vin, kout, vout, wb + L.off_tmp_k, HAS_V ? (void *)(wb + L.off_tmp_v) : nullptr};
