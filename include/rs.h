@@ -221,6 +221,30 @@ rs_status rs_sort(rs_context *ctx, rs_key_type key_type, uint32_t order, const v
                   const void *vals_in, void *keys_out, void *vals_out, uint64_t n, void *ws,
                   size_t ws_bytes, void *stream);
 
+/*
+ * rs_sort for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and result as rs_sort, without ws / ws_bytes: the scratch
+ * (control block, histograms, look-back words and the ping-pong copy) is a
+ * fixed device array inside the library, rs_sort_noalloc_scratch_bytes()
+ * bytes (64 MiB) on each GPU it runs on, held until the process ends.  The
+ * call allocates nothing (no hipMalloc, no hipFree, no profiling events).
+ * A sort whose workspace (rs_workspace_bytes) exceeds that size is rejected
+ * with RS_ERR_UNSUPPORTED before any HIP call: about 16M 32-bit keys, 8M
+ * 32-bit pairs or 64-bit keys, 4M 64-bit pairs.  Every call on one GPU
+ * shares that GPU's array and clears what must start at zero itself; calls
+ * that overlap in time on one GPU (other streams, other host threads) race
+ * and must not be made.  Device-side errors: rs_workspace_status is not
+ * available for this scratch (the call never waits longer than the bound of
+ * rs_debug_wait_set and then leaves an invalid output).
+ */
+rs_status rs_sort_noalloc(rs_context *ctx, rs_key_type key_type, uint32_t order,
+                          const void *keys_in, const void *vals_in, void *keys_out,
+                          void *vals_out, uint64_t n, void *stream);
+
+/* Bytes of the fixed scratch array of rs_sort_noalloc. */
+uint64_t rs_sort_noalloc_scratch_bytes(void);
+
 /* rs_segmented_sort with a key order; same arguments otherwise. */
 rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_t order,
                                   const void *keys_in, const void *vals_in, void *keys_out,

@@ -49,6 +49,7 @@ EXPORTED = (
     "rs_sort", "rs_segmented_sort_order", "rs_merge_sort", "rs_merge_workspace_bytes",
     "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get",
     "rs_workspace_status", "rs_debug_wait_set", "rs_debug_sort_stages",
+    "rs_sort_noalloc", "rs_sort_noalloc_scratch_bytes",
 )
 
 
@@ -115,6 +116,10 @@ def lib():
             L.rs_workspace_status.argtypes = [vp, vp, vp]
             L.rs_debug_wait_set.argtypes = [vp, u32, u32]
             L.rs_debug_sort_stages.argtypes = [vp, ci, vp, vp, vp, vp, u64, ci, vp, vp, sz, vp]
+            L.rs_sort_noalloc.argtypes = [vp, ci, u32, vp, vp, vp, vp, u64, vp]
+            L.rs_sort_noalloc.restype = ci
+            L.rs_sort_noalloc_scratch_bytes.argtypes = []
+            L.rs_sort_noalloc_scratch_bytes.restype = u64
             for name in ("rs_context_create", "rs_workspace_bytes", "rs_sort_keys_u32",
                          "rs_sort_keys_u64", "rs_sort_pairs_u32", "rs_sort_pairs_u64",
                          "rs_segmented_sort", "rs_segmented_workspace_bytes",

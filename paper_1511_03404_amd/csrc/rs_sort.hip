@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -912,6 +913,42 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     return RS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of rs_sort_noalloc: a fixed device array instead of an allocation.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory: its
+// device address comes from hipGetSymbolAddress, once per device, and only
+// that address is handed to kernels.
+
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// The device address of this device's copy of `scratch` (the device must be
+// current).  Looked up on the first call for a device, then reused.
+static rs_status scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return fail(RS_ERR_UNSUPPORTED, "device %d is beyond the %d the library tracks", device,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(RS_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return RS_OK;
+}
+
 // ===========================================================================
 // Exported C-ABI.
 
@@ -1088,6 +1125,53 @@ rs_status rs_sort(rs_context *ctx, rs_key_type key_type, uint32_t order, const v
                                         stream, kmap);
     return run_sort<uint64_t, false>(ctx, (const uint64_t *)keys_in, nullptr, (uint64_t *)keys_out,
                                      nullptr, n, ws, ws_bytes, stream, kmap);
+}
+
+rs_status rs_sort_noalloc(rs_context *ctx, rs_key_type key_type, uint32_t order,
+                          const void *keys_in, const void *vals_in, void *keys_out,
+                          void *vals_out, uint64_t n, void *stream)
+{
+    if (!ctx)
+        return fail(RS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+    rs_status st;
+    (void)order_map(key_type, order, &st);
+    if (st != RS_OK)
+        return st;
+    if ((vals_in != nullptr) != (vals_out != nullptr))
+        return fail(RS_ERR_INVALID_ARGUMENT, "vals_in and vals_out must both be given or both NULL");
+    if (n >= RS_MAX_ELEMENTS)
+        return fail(RS_ERR_UNSUPPORTED, "n = %llu exceeds the limit of 2^30 - 1 elements",
+                    (unsigned long long)n);
+    if (n == 0)
+        return RS_OK;
+    const int kb = key_type == RS_KEY_U32 ? 4 : 8;
+    const bool has_v = vals_in != nullptr;
+    const uint64_t need = make_layout(kb, has_v, n, pick_sort(ctx, kb, has_v, n)).total;
+    if (need > kNoAllocScratchBytes)
+        return fail(RS_ERR_UNSUPPORTED,
+                    "n = %llu needs %llu bytes of scratch, above the fixed %llu of "
+                    "rs_sort_noalloc (use rs_sort with a workspace)",
+                    (unsigned long long)n, (unsigned long long)need,
+                    (unsigned long long)kNoAllocScratchBytes);
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return fail(RS_ERR_DEVICE, "cannot select HIP device %d", ctx->device);
+    void *ws = nullptr;
+    st = scratch_address(ctx->device, &ws);
+    if (st != RS_OK)
+        return st;
+    // no profiling events either: nothing is created on this path
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    st = rs_sort(ctx, key_type, order, keys_in, vals_in, keys_out, vals_out, n, ws,
+                 kNoAllocScratchBytes, stream);
+    ctx->prof = prof;
+    return st;
+}
+
+uint64_t rs_sort_noalloc_scratch_bytes(void)
+{
+    return kNoAllocScratchBytes;
 }
 
 rs_status rs_segmented_sort_order(rs_context *ctx, rs_key_type key_type, uint32_t order,

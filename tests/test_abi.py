@@ -24,7 +24,7 @@ def declared_functions():
     for fn in os.listdir(os.path.join(ROOT, "include")):
         if fn.endswith(".h"):
             text = open(os.path.join(ROOT, "include", fn)).read()
-            names += re.findall(r"^\s*(?:rs_status|void|const char \*)\s*\*?\s*(rs_\w+)\s*\(",
+            names += re.findall(r"^\s*(?:rs_status|void|uint64_t|const char \*)\s*\*?\s*(rs_\w+)\s*\(",
                                 text, flags=re.M)
     return sorted(set(names))
 
@@ -291,3 +291,22 @@ def test_status_query_and_test_entry_points_validate_on_the_host(rs, ctx):
     assert st(ctx.handle, 0, fake, fake + (1 << 21), fake + (1 << 20), None, 100, 1, None, None,
               0, None) == rs.RS_ERR_INVALID_ARGUMENT
     assert st(ctx.handle, 0, None, None, None, None, 0, 2, None, None, 0, None) == rs.RS_OK
+
+
+def test_noalloc_rejects_what_its_scratch_cannot_hold(rs, ctx):
+    """rs_sort_noalloc validates on the host: sizes whose workspace exceeds
+    the fixed scratch are refused before any HIP call."""
+    L = rs.lib()
+    fake = 0x7F0000000000
+    cap = L.rs_sort_noalloc_scratch_bytes()
+    assert cap == 64 << 20
+    n = 1 << 24  # 32-bit pairs: 128 MiB of ping-pong copy alone
+    assert ctx.workspace_bytes(32, True, n) > cap
+    assert L.rs_sort_noalloc(ctx.handle, 0, 0, fake, fake + (1 << 28), fake + (2 << 28),
+                             fake + (3 << 28), n, None) == rs.RS_ERR_UNSUPPORTED
+    assert b"scratch" in L.rs_last_error()
+    assert L.rs_sort_noalloc(ctx.handle, 0, 0, fake, None, fake + (1 << 28), fake, 10,
+                             None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_sort_noalloc(None, 0, 0, fake, None, fake, None, 10,
+                             None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_sort_noalloc(ctx.handle, 0, 0, None, None, None, None, 0, None) == rs.RS_OK
