@@ -296,8 +296,9 @@ rs_status rs_merge_workspace_bytes(const rs_context *ctx, rs_key_type key_type, 
  * keys are cut into r-bit digits and sorted with one counting sort per
  * digit; the result does not depend on r).  The library is compiled for a
  * fixed list of configurations per key type and values/no values: r of 4 to
- * 8 bits (ceil(key bits / r) digit passes) and tile shapes of threads x
- * items elements per workgroup.  Index 0 of each list is the default.  Each
+ * 8 bits and of 11 bits (ceil(key bits / r) digit passes: three for 32-bit
+ * keys at 11 bits) and tile shapes of threads x items elements per
+ * workgroup.  Index 0 of each list is the default.  Each
  * context holds a tune table that picks one configuration per key type,
  * values or not, plain or segmented sort, and size class ceil(log2 n) (n of
  * the plain sort, `total` of the segmented one).  Sorts that fit one
@@ -306,13 +307,18 @@ rs_status rs_merge_workspace_bytes(const rs_context *ctx, rs_key_type key_type, 
  * table says.  Every configuration gives the same, bit-exact result.
  */
 typedef struct rs_config {
-    int radix_bits; /* digit width r, 4..8 */
+    int radix_bits; /* digit width r, 4..11 */
     int threads;    /* workgroup size of the digit pass */
     int items;      /* elements per thread; a tile holds threads * items */
 } rs_config;
 
 /* Number of compiled configurations for this key type, with/without values. */
 rs_status rs_config_count(rs_key_type key_type, int has_values, int *count);
+
+/* How many of them (the first *count of the list) the segmented sort can
+ * use: the configurations with digits of more than 8 bits are compiled for
+ * the plain sort only. */
+rs_status rs_segmented_config_count(rs_key_type key_type, int has_values, int *count);
 
 /* Configuration `index` (0 <= index < count) of that list. */
 rs_status rs_config_get(rs_key_type key_type, int has_values, int index, rs_config *config);

@@ -49,7 +49,7 @@ EXPORTED = (
     "rs_sort", "rs_segmented_sort_order", "rs_merge_sort", "rs_merge_workspace_bytes",
     "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get",
     "rs_workspace_status", "rs_debug_wait_set", "rs_debug_sort_stages",
-    "rs_sort_noalloc", "rs_sort_noalloc_scratch_bytes",
+    "rs_sort_noalloc", "rs_sort_noalloc_scratch_bytes", "rs_segmented_config_count",
 )
 
 
@@ -103,6 +103,8 @@ def lib():
             L.rs_last_error.argtypes = []
             L.rs_last_error.restype = ctypes.c_char_p
             L.rs_config_count.argtypes = [ci, ci, ctypes.POINTER(ci)]
+            L.rs_segmented_config_count.argtypes = [ci, ci, ctypes.POINTER(ci)]
+            L.rs_segmented_config_count.restype = ci
             L.rs_config_get.argtypes = [ci, ci, ci, ctypes.POINTER(Config)]
             L.rs_tune_set.argtypes = [vp, ci, ci, ci, ci, ci]
             L.rs_tune_get.argtypes = [vp, ci, ci, ci, ci, ctypes.POINTER(ci)]
@@ -251,12 +253,14 @@ class Context:
         return [(names[i].decode(), tags[i], ms[i]) for i in range(m)]
 
 
-def configs(key_bits: int, has_values: bool) -> list[dict]:
+def configs(key_bits: int, has_values: bool, segmented: bool = False) -> list[dict]:
     """The compiled digit-pass configurations for this kind, in index order
-    (index 0 is the default)."""
+    (index 0 is the default); segmented=True: those the segmented sort can
+    use (a prefix of the list)."""
     kt = RS_KEY_U32 if key_bits == 32 else RS_KEY_U64
     n = ctypes.c_int()
-    _check(lib().rs_config_count(kt, int(has_values), ctypes.byref(n)))
+    f = lib().rs_segmented_config_count if segmented else lib().rs_config_count
+    _check(f(kt, int(has_values), ctypes.byref(n)))
     out = []
     for i in range(n.value):
         c = Config()

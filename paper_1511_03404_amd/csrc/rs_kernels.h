@@ -46,8 +46,11 @@ constexpr int kBallotShare = 4;
 // the digit runs of the scatter longer.
 template <int R, int THREADS, int ITEMS>
 struct PassCfg {
-    static_assert(R >= 4 && R <= 8, "digit widths of 4..8 bits");
+    static_assert(R >= 4 && R <= 11, "digit widths of 4..11 bits");
     static_assert(THREADS % kWave == 0 && THREADS >= 256 && THREADS <= 1024, "256..1024 threads");
+    static_assert(R <= 8 || THREADS == 1024, "wide digits use 1024-thread tiles");
+    // digits of more than 8 bits take the wide layout (rs_wide.h)
+    static constexpr bool kWide = R > 8;
     static constexpr int kRadixBits = R;
     static constexpr int kBins = 1 << R;
     static constexpr int kThreads = THREADS;
@@ -102,23 +105,34 @@ struct HistArgs {
 // kWave; spread digits mostly land in different banks.
 constexpr int kHistCols = 16;
 
-template <int R>
+// Columns per bin for D digit positions of R bits: 16 up to 8-bit digits;
+// wide digits have 8x the bins, so fewer columns keep the table within
+// 96 KB (4 for 32-bit keys at 11 bits, 2 for 64-bit keys).
+template <int D, int R>
+constexpr int hist_cols()
+{
+    if (R <= 8)
+        return kHistCols;
+    return (size_t)D * (1u << R) * 4 * 4 <= 96 * 1024 ? 4 : 2;
+}
+
+template <int R, int COLS = kHistCols>
 __device__ __forceinline__ void hist_add(uint32_t *tab, int p, uint32_t dg, uint32_t col)
 {
-    atomicAdd(&tab[(((uint32_t)p << R) + dg) * kHistCols + col], 1u);
+    atomicAdd(&tab[(((uint32_t)p << R) + dg) * COLS + col], 1u);
 }
 
 // Adds the counters into hist ([d][2^R]).  Row r (position r >> R, bin
 // r % 2^R) is summed by one thread, which starts at column r so that
 // neighbouring threads read different banks.
-template <int D, int R>
+template <int D, int R, int COLS = kHistCols>
 __device__ __forceinline__ void hist_flush(const uint32_t *tab, uint32_t *hist, uint32_t t)
 {
     for (uint32_t r = t; r < (uint32_t)D << R; r += kHistThreads) {
         uint32_t s = 0;
 #pragma unroll
-        for (uint32_t c = 0; c < kHistCols; ++c)
-            s += tab[r * kHistCols + ((c + r) & (kHistCols - 1))];
+        for (uint32_t c = 0; c < COLS; ++c)
+            s += tab[r * COLS + ((c + r) & (COLS - 1))];
         if (s)
             atomicAdd(&hist[r], s);
     }
@@ -132,11 +146,12 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
     constexpr int VPT = 16 / KPV;             // vectors per thread per batch
     constexpr int NK = VPT * KPV;             // 16 keys per thread per batch
     constexpr uint32_t BATCH = kHistThreads * VPT;
-    constexpr uint32_t TAB = (D << R) * kHistCols;
+    constexpr int COLS = hist_cols<D, R>();
+    constexpr uint32_t TAB = (D << R) * COLS;
     __shared__ uint32_t tab[TAB];
 
     const uint32_t t = threadIdx.x;
-    const uint32_t col = t % kHistCols;
+    const uint32_t col = t % COLS;
     for (uint32_t i = t; i < TAB; i += kHistThreads)
         tab[i] = 0;
 
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
         for (int p = 0; p < D; ++p) {
 #pragma unroll
             for (int i = 0; i < NK; ++i)
-                hist_add<R>(tab, p, digit_of<R>(key[i], p * R), col);
+                hist_add<R, COLS>(tab, p, digit_of<R>(key[i], p * R), col);
         }
     }
     // the rest: unaligned head, vectors after the last full batch, ragged
@@ -190,10 +205,10 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
         const K key = map_in(keys[idx], a.kmap);
 #pragma unroll
         for (int p = 0; p < D; ++p)
-            hist_add<R>(tab, p, digit_of<R>(key, p * R), col);
+            hist_add<R, COLS>(tab, p, digit_of<R>(key, p * R), col);
     }
     __syncthreads();
-    hist_flush<D, R>(tab, a.hist, t);
+    hist_flush<D, R, COLS>(tab, a.hist, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,25 +233,44 @@ __global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
 {
     constexpr int D = num_passes<K, R>();
     constexpr int NB = 1 << R;
+    // bins per thread: up to 256 bins one each, wide digits several
+    // consecutive bins per thread
+    constexpr int BPT = NB > kRadix ? NB / kRadix : 1;
+    constexpr int SCAN = NB > kRadix ? kRadix : NB;
     __shared__ uint32_t s_tmp[8];
     __shared__ int s_trivial[D];
     __shared__ int s_skewed[D];
     __shared__ unsigned long long s_sq[kRadix / kWave];
     const uint32_t t = threadIdx.x;
+    const bool active = t * BPT < (uint32_t)NB;
     // every row's load in flight at once, not one latency per digit position
-    uint32_t cnt[D];
+    uint32_t cnt[D][BPT];
 #pragma unroll
     for (int p = 0; p < D; ++p)
-        cnt[p] = t < (uint32_t)NB ? a.hist[p * NB + t] : 0u;
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+            cnt[p][i] = active ? a.hist[p * NB + t * BPT + i] : 0u;
 #pragma unroll
     for (int p = 0; p < D; ++p) {
-        const uint32_t c = cnt[p];
-        const uint32_t ex = bins_exclusive_scan<NB>(c, s_tmp);
-        if (t < (uint32_t)NB)
-            a.digit_base[p * NB + t] = ex;
-        const int triv = __syncthreads_or(c == a.n);
+        uint32_t sum = 0;
+        bool full = false;
+        unsigned long long sq = 0;
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            sum += cnt[p][i];
+            full = full || cnt[p][i] == a.n;
+            sq += (unsigned long long)cnt[p][i] * cnt[p][i];
+        }
+        uint32_t ex = bins_exclusive_scan<SCAN>(sum, s_tmp);
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                a.digit_base[p * NB + t * BPT + i] = ex;
+                ex += cnt[p][i];
+            }
+        }
+        const int triv = __syncthreads_or(full);
         // chance that two keys share this digit: sum_b (c_b / n)^2
-        unsigned long long sq = (unsigned long long)c * c;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
             sq += __shfl_xor(sq, off);
@@ -303,6 +337,7 @@ struct PassArgs {
     uint32_t *ctrl;
     const uint32_t *digit_base;  // row of this pass
     uint32_t *status;            // [tiles][2^R] of this pass
+    uint32_t *gagg;              // [tiles / kGroup][2^R] group aggregates (see lookback_digit)
     uint32_t *claims;            // per-XCD claim counters and group lists
     uint32_t num_tiles;
     uint32_t num_groups;
@@ -491,6 +526,130 @@ __device__ __forceinline__ void load_tile(const K *tk, const V *tv, uint32_t val
     }
 }
 
+// Group aggregate word of the two-level look-back: [31:24] how many tiles
+// of the group have added their count, [23:0] the sum of those counts (a
+// group holds at most kClaimGroup x 16384 < 2^24 elements).
+constexpr uint32_t kGroupTileOne = 1u << 24;
+constexpr uint32_t kGroupCountMask = kGroupTileOne - 1;
+
+// Exclusive prefix of digit d over tiles [first_tile, tile): the counting
+// sort's running offset of this tile (Section 2.6), found by a decoupled
+// look-back over the status words of earlier tiles.
+//
+// Flat form (gagg == nullptr): read LBW predecessors per round trip, add
+// their counts in order up to the first inclusive word; on a tile that has
+// not published yet, wait and re-read from there.
+//
+// Two-level form: tiles form groups of GROUP consecutive tiles (the tiles
+// one XCD claims together, so a group's tiles run at the same time), and
+// every tile also adds its count to its group's aggregate word.  The walk
+// goes tile by tile only inside the tile's own group; before the group it
+// takes a whole group per step: the inclusive word of the group's last tile
+// if published (then done), else the group's aggregate once all GROUP
+// tiles are in it.  A walk over the many tiles in flight then takes few
+// round trips of LBW words each, not one per LBW tiles.  (Reading the whole
+// group and several earlier groups in one round trip measured slower: the
+// wait is mostly for the group's own earlier tiles to publish their counts,
+// not for round trips.)
+//
+// Every wait is bounded: after wait.spin_limit rounds without progress the
+// error word records kErrWait and the prefix found so far is returned.
+template <int LBW, int GROUP>
+__device__ __forceinline__ uint32_t lookback_digit(const uint32_t *status, const uint32_t *gagg,
+                                                   uint32_t nb, uint32_t d, uint32_t tile,
+                                                   uint32_t first_tile, const PassArgs &wait)
+{
+    uint32_t prefix = 0;
+    uint32_t spins = 0;
+    const bool stall = (wait.stall & kStallLookback) != 0;
+    const int64_t glo = gagg ? std::max<int64_t>(first_tile, (int64_t)(tile - tile % GROUP))
+                             : (int64_t)first_tile;
+    // tiles of this group before this one (all earlier tiles in flat form)
+    int64_t k = (int64_t)tile - 1;
+    while (k >= glo) {
+        uint32_t st[LBW];
+#pragma unroll
+        for (int i = 0; i < LBW; ++i)
+            st[i] = (k - i >= glo) ? __hip_atomic_load(&status[(uint64_t)(k - i) * nb + d],
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                   : 0u;
+        int used = 0;
+        bool done = false;
+        if (!stall) {
+#pragma unroll
+            for (int i = 0; i < LBW; ++i) {
+                if (!done && used == i && k - i >= glo) {
+                    const uint32_t f = st[i] & kFlagMask;
+                    if (f != 0) {
+                        prefix += st[i] & kCountMask;
+                        done = f == kFlagInc;
+                        used = i + 1;
+                    }
+                }
+            }
+        }
+        if (done)
+            return prefix;
+        k -= used;
+        if (k < glo)
+            break;
+        if (used == 0 && ++spins > wait.spin_limit) {
+            atomicOr(wait.err, kErrWait);
+            return prefix;
+        }
+        if (used < LBW)
+            __builtin_amdgcn_s_sleep(1);
+    }
+    if (!gagg)
+        return prefix;  // reached first_tile: no earlier tile
+    // earlier groups, newest first, LBW per round trip
+    int64_t g = (int64_t)(tile / GROUP) - 1;
+    const int64_t g_lo = (int64_t)(first_tile / GROUP);
+    while (g >= g_lo) {
+        uint32_t last[LBW], agg[LBW];
+#pragma unroll
+        for (int i = 0; i < LBW; ++i) {
+            const bool in = g - i >= g_lo;
+            const uint64_t gi = (uint64_t)(in ? g - i : 0);
+            last[i] = in ? __hip_atomic_load(&status[(gi * GROUP + GROUP - 1) * nb + d],
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : 0u;
+            agg[i] = in ? __hip_atomic_load(&gagg[gi * nb + d], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
+        }
+        int used = 0;
+        bool done = false;
+        if (!stall) {
+#pragma unroll
+            for (int i = 0; i < LBW; ++i) {
+                if (!done && used == i && g - i >= g_lo) {
+                    if ((last[i] & kFlagMask) == kFlagInc) {
+                        prefix += last[i] & kCountMask;
+                        done = true;
+                        used = i + 1;
+                    } else if ((agg[i] >> 24) == (uint32_t)GROUP) {
+                        prefix += agg[i] & kGroupCountMask;
+                        used = i + 1;
+                    }
+                }
+            }
+        }
+        if (done)
+            return prefix;
+        g -= used;
+        if (g < g_lo)
+            break;
+        if (used == 0 && ++spins > wait.spin_limit) {
+            atomicOr(wait.err, kErrWait);
+            return prefix;
+        }
+        if (used < LBW)
+            __builtin_amdgcn_s_sleep(1);
+    }
+    return prefix;
+}
+
 // A staged (key, value) pair: one 8- or 16-byte LDS word.
 template <typename K>
 struct alignas(2 * sizeof(K)) KvPair {
@@ -507,7 +666,7 @@ template <typename K, typename C, bool HAS_V>
 struct PassLds {
     static constexpr int W = C::kThreads / kWave;
     static constexpr size_t kStageBytes = (size_t)C::kTile * sizeof(K);
-    static_assert((size_t)W * C::kBins * 8 <= kStageBytes,
+    static_assert(C::kWide || (size_t)W * C::kBins * 8 <= kStageBytes,
                   "the lane-mask tables live in the staging buffer");
     uint32_t wcnt[W * C::kBins];  // per wave and digit: count, then base in tile
     uint32_t gbase[C::kBins];
@@ -527,10 +686,10 @@ struct PassLds {
 template <typename K, typename V, bool HAS_V, typename C, typename Hook>
 __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, const V *tv, K *dk,
                                           V *dv, uint32_t valid, uint32_t limit, uint32_t tile,
-                                          uint32_t first_tile, uint32_t *status, uint32_t dbase,
-                                          int shift, bool ballot_rank, uint32_t map_load,
-                                          uint32_t map_store, const PassArgs &wait,
-                                          Hook &&after_lookback)
+                                          uint32_t first_tile, uint32_t *status, uint32_t *gagg,
+                                          uint32_t dbase, int shift, bool ballot_rank,
+                                          uint32_t map_load, uint32_t map_store,
+                                          const PassArgs &wait, Hook &&after_lookback)
 {
     constexpr int R = C::kRadixBits;
     constexpr uint32_t NB = C::kBins;
@@ -589,6 +748,10 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
         __hip_atomic_store(&status[(uint64_t)tile * NB + t],
                            (tile == first_tile ? kFlagInc : kFlagAgg) | cnt, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+        if (gagg)
+            __hip_atomic_fetch_add(&gagg[(uint64_t)(tile / C::kGroup) * NB + t],
+                                   kGroupTileOne | cnt, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     const uint32_t excl = bins_exclusive_scan<NB>(cnt, L.tmp);
     if (t < NB) {
@@ -615,48 +778,11 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
         }
     }
     if (t < NB) {
-        // decoupled look-back: read LBW predecessors per round trip, add
-        // their counts in order up to the first inclusive one; on a tile
-        // that has not published yet, wait and re-read from there (at most
-        // wait.spin_limit rounds without progress: then the error word
-        // records kErrWait and the tile goes on with the prefix it has)
-        uint32_t prefix = 0;
-        int64_t k = (int64_t)tile - 1;
-        const int64_t lo = first_tile;
-        uint32_t spins = 0;
-        while (k >= lo) {
-            uint32_t st[LBW];
-#pragma unroll
-            for (int i = 0; i < LBW; ++i)
-                st[i] = (k - i >= lo)
-                            ? __hip_atomic_load(&status[(uint64_t)(k - i) * NB + t],
-                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : kFlagInc;
-            int used = 0;
-            bool done = false;
-            if (!(wait.stall & kStallLookback)) {
-#pragma unroll
-                for (int i = 0; i < LBW; ++i) {
-                    if (!done && used == i) {
-                        const uint32_t f = st[i] & kFlagMask;
-                        if (f != 0) {
-                            prefix += st[i] & kCountMask;
-                            done = f == kFlagInc;
-                            used = i + 1;
-                        }
-                    }
-                }
-            }
-            if (done)
-                break;
-            k -= used;
-            if (used == 0 && ++spins > wait.spin_limit) {
-                atomicOr(wait.err, kErrWait);
-                break;
-            }
-            if (used < LBW)
-                __builtin_amdgcn_s_sleep(1);
-        }
+        // decoupled look-back over the tiles before this one
+        const uint32_t prefix =
+            tile == first_tile
+                ? 0u
+                : lookback_digit<LBW, C::kGroup>(status, gagg, NB, t, tile, first_tile, wait);
         if (tile != first_tile)
             __hip_atomic_store(&status[(uint64_t)tile * NB + t], kFlagInc | (prefix + cnt),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -708,12 +834,19 @@ __device__ __forceinline__ void pass_tile(PassLds<K, C, HAS_V> &L, const K *tk, 
     __syncthreads();  // LDS is reused by the next tile
 }
 
+}  // namespace rs
+
+#include "rs_wide.h"
+
+namespace rs {
+
 template <typename K, typename V, bool HAS_V, typename C>
 __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
 {
     constexpr int THREADS = C::kThreads;
     constexpr int T = C::kTile;
-    __shared__ PassLds<K, C, HAS_V> L;
+    using Lds = std::conditional_t<C::kWide, WideLds<K, C, HAS_V>, PassLds<K, C, HAS_V>>;
+    __shared__ Lds L;
 
     const uint32_t t = threadIdx.x;
     const uint32_t plan = a.ctrl[kCtrlPlan + a.pass];
@@ -741,8 +874,17 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
     const V *sv = HAS_V ? pick<const V>(a.b, src, true) : nullptr;
     K *dk = pick<K>(a.b, dstb, false);
     V *dv = HAS_V ? pick<V>(a.b, dstb, true) : nullptr;
-    // this digit's starting offset, fetched early (used after the look-back)
-    const uint32_t dbase = t < (uint32_t)C::kBins ? a.digit_base[t] : 0u;
+    // the starting offsets of this thread's digits, fetched early (used
+    // after the look-back): digit t, or digits 2t and 2t+1 of a wide pass
+    uint32_t dbase = 0;
+    uint32_t db[2] = {0, 0};
+    if constexpr (C::kWide) {
+        const uint2 d2 = ((const uint2 *)a.digit_base)[t];
+        db[0] = d2.x;
+        db[1] = d2.y;
+    } else {
+        dbase = t < (uint32_t)C::kBins ? a.digit_base[t] : 0u;
+    }
     const uint32_t xcc = t == 0 ? xcc_id() : 0u;
     // the next tile is claimed once the current tile's look-back is done:
     // the claim's round trips overlap the writes, and the workgroup waits
@@ -758,13 +900,22 @@ __global__ __launch_bounds__(C::kThreads) void k_pass(PassArgs a)
             break;
         const uint64_t tb = (uint64_t)tile * T;
         const uint32_t valid = (uint32_t)std::min<uint64_t>(T, a.n - tb);
-        pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n, tile,
-                                  0, a.status, dbase, a.shift, (plan & kPlanBallot) != 0,
-                                  (plan & kPlanFirst) ? a.kmap : 0u,
-                                  (plan & kPlanLast) ? a.kmap : 0u, a, [&](uint32_t tt) {
-                                      if (tt == 0)
-                                          L.tile = claim_tile<C::kGroup>(a, xcc);
-                                  });
+        auto claim_next = [&](uint32_t tt) {
+            if (tt == 0)
+                L.tile = claim_tile<C::kGroup>(a, xcc);
+        };
+        if constexpr (C::kWide)
+            pass_tile_wide<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid,
+                                           a.n, tile, 0, a.status, db, a.shift,
+                                           (plan & kPlanBallot) != 0,
+                                           (plan & kPlanFirst) ? a.kmap : 0u,
+                                           (plan & kPlanLast) ? a.kmap : 0u, a, claim_next);
+        else
+            pass_tile<K, V, HAS_V, C>(L, sk + tb, HAS_V ? sv + tb : nullptr, dk, dv, valid, a.n,
+                                      tile, 0, a.status, a.gagg, dbase, a.shift,
+                                      (plan & kPlanBallot) != 0,
+                                      (plan & kPlanFirst) ? a.kmap : 0u,
+                                      (plan & kPlanLast) ? a.kmap : 0u, a, claim_next);
     }
 }
 
@@ -952,7 +1103,7 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
                                   HAS_V ? (const V *)a.src_v + off : nullptr,
                                   (K *)a.dst_k + rec.start,
                                   HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
-                                  tile, rec.tile_start, a.status, dbase, a.shift, false,
+                                  tile, rec.tile_start, a.status, nullptr, dbase, a.shift, false,
                                   a.map_load, a.map_store, pa, [](uint32_t) {});
     }
 }

@@ -246,8 +246,9 @@ struct Layout {
     uint32_t tile;
     uint64_t tiles;
     uint64_t off_ctrl, off_hist, off_base, off_status, off_tmp_k, off_tmp_v, total;
-    uint64_t status_bytes;  // look-back words and claim counters of all passes
+    uint64_t status_bytes;  // look-back words, claim counters, group aggregates of all passes
     uint64_t claim_words;
+    uint64_t groups;        // tile groups of the two-level look-back
 };
 
 static Layout make_layout(int key_bytes, bool has_values, uint64_t n, const SortOps &op)
@@ -266,7 +267,9 @@ static Layout make_layout(int key_bytes, bool has_values, uint64_t n, const Sort
     o = align_up(o + (uint64_t)L.d * L.bins * 4, 256);
     L.off_status = o;
     L.claim_words = kXcdSlots * (1 + L.tiles);  // per-XCD counters + per-XCD group lists
-    L.status_bytes = align_up((uint64_t)L.d * (L.tiles * L.bins + L.claim_words) * 4, 16);
+    L.groups = (L.tiles + kClaimGroup - 1) / kClaimGroup;
+    L.status_bytes = align_up(
+        (uint64_t)L.d * (L.tiles * L.bins + L.claim_words + L.groups * L.bins) * 4, 16);
     o = align_up(o + L.status_bytes, 256);
     L.off_tmp_k = o;
     o = align_up(o + n * key_bytes, 256);
@@ -556,6 +559,8 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
         pa.digit_base = base + p * L.bins;
         pa.status = status + (uint64_t)p * L.tiles * L.bins;
         pa.claims = status + (uint64_t)L.d * L.tiles * L.bins + (uint64_t)p * L.claim_words;
+        pa.gagg = status + (uint64_t)L.d * (L.tiles * L.bins + L.claim_words) +
+                  (uint64_t)p * L.groups * L.bins;
         pa.num_tiles = (uint32_t)L.tiles;
         pa.num_groups = (uint32_t)((L.tiles + kClaimGroup - 1) / kClaimGroup);
         pa.kmap = kmap;
@@ -1386,6 +1391,16 @@ rs_status rs_config_count(rs_key_type key_type, int has_values, int *count)
     return RS_OK;
 }
 
+rs_status rs_segmented_config_count(rs_key_type key_type, int has_values, int *count)
+{
+    if (!count)
+        return fail(RS_ERR_INVALID_ARGUMENT, "count is NULL");
+    if (key_type != RS_KEY_U32 && key_type != RS_KEY_U64)
+        return fail(RS_ERR_INVALID_ARGUMENT, "unknown key type %d", (int)key_type);
+    (void)seg_table(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, count);
+    return RS_OK;
+}
+
 rs_status rs_config_get(rs_key_type key_type, int has_values, int index, rs_config *config)
 {
     if (!config)
@@ -1414,10 +1429,15 @@ rs_status rs_tune_set(rs_context *ctx, rs_key_type key_type, int has_values, int
         return fail(RS_ERR_INVALID_ARGUMENT, "size_log2 %d outside [-1, %d)", size_log2,
                     kTuneClasses);
     int count = 0;
-    (void)sort_table(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, &count);
+    // the segmented sort's list is the prefix of the plain sort's without
+    // the wide-digit configurations
+    if (segmented)
+        (void)seg_table(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, &count);
+    else
+        (void)sort_table(key_type == RS_KEY_U32 ? 4 : 8, has_values != 0, &count);
     if (index < -1 || index >= count)
-        return fail(RS_ERR_INVALID_ARGUMENT, "configuration index %d outside [-1, %d)", index,
-                    count);
+        return fail(RS_ERR_INVALID_ARGUMENT, "configuration index %d outside [-1, %d)%s", index,
+                    count, segmented ? " for the segmented sort" : "");
     int8_t *row = ctx->tune[key_type == RS_KEY_U64][has_values != 0][segmented != 0];
     for (int c = 0; c < kTuneClasses; ++c)
         if (size_log2 < 0 || c == size_log2)

@@ -9,8 +9,8 @@ namespace rs {
 
 const SegOps *seg_ops_u32(bool has_values, int *count)
 {
-    static const SegOps keys[] = {RS_CONFIGS_U32_KEYS(RS_KEYS_OPS)};
-    static const SegOps pairs[] = {RS_CONFIGS_U32_PAIRS(RS_PAIRS_OPS)};
+    static const SegOps keys[] = {RS_SEG_CONFIGS_U32_KEYS(RS_KEYS_OPS)};
+    static const SegOps pairs[] = {RS_SEG_CONFIGS_U32_PAIRS(RS_PAIRS_OPS)};
     if (has_values) {
         *count = (int)(sizeof pairs / sizeof pairs[0]);
         return pairs;

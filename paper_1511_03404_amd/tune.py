@@ -1,5 +1,5 @@
-"""Autotuner of the digit-pass configuration: digit width r (4..8 bits) and
-tile shape (threads x items per thread).
+"""Autotuner of the digit-pass configuration: digit width r (4..8 or 11
+bits) and tile shape (threads x items per thread).
 
 The radix sort's result does not depend on r (paper, Section 2.6: the keys
 are cut into r-bit digits and every digit is a stable counting sort), so
@@ -57,8 +57,8 @@ def _uniform_keys(n: int, bits: int, device, seed: int) -> torch.Tensor:
     return (hi << 32) | (lo & 0xFFFFFFFF)
 
 
-def _candidates(key_bits, has_values, candidates):
-    cfgs = configs(key_bits, has_values)
+def _candidates(key_bits, has_values, candidates, segmented=False):
+    cfgs = configs(key_bits, has_values, segmented)
     idx = list(range(len(cfgs))) if candidates is None else list(candidates)
     for i in idx:
         if not 0 <= i < len(cfgs):
@@ -134,7 +134,7 @@ def tune_segmented(keys: torch.Tensor, values: torch.Tensor | None, offsets: tor
     has_v = values is not None
     total = keys.numel()
     nseg = offsets.numel() - 1
-    cfgs, idx = _candidates(bits, has_v, candidates)
+    cfgs, idx = _candidates(bits, has_v, candidates, segmented=True)
     cls = size_class(total)
     ko = torch.empty_like(keys)
     vo = torch.empty_like(values) if has_v else None

@@ -116,16 +116,24 @@ def test_python_binding_rejects_host_tensors(rs):
 
 def test_compiled_configurations(rs):
     """Every kind has its list: the default (index 0) at 8-bit digits, every
-    digit width of 4..8 bits, tiles within one workgroup's limits."""
+    digit width of 4..8 bits and 11-bit digits, tiles within one workgroup's
+    limits; the segmented sort's list is the prefix without the wide digits."""
     for bits in (32, 64):
         for pairs in (False, True):
             cfgs = rs.configs(bits, pairs)
+            seg = rs.configs(bits, pairs, segmented=True)
             assert cfgs[0]["radix_bits"] == 8
-            assert {c["radix_bits"] for c in cfgs} == {4, 5, 6, 7, 8}
+            assert {c["radix_bits"] for c in cfgs} == {4, 5, 6, 7, 8, 11}
+            assert seg == cfgs[:len(seg)] and {c["radix_bits"] for c in seg} == {4, 5, 6, 7, 8}
             for c in cfgs:
                 assert 256 <= c["threads"] <= 1024 and c["threads"] % 64 == 0
-                assert c["items"] >= 2 ** c["radix_bits"] // 32  # lane-mask tables fit the staging
                 assert c["threads"] * c["items"] * bits // 8 <= 128 * 1024
+                if c["radix_bits"] <= 8:
+                    # the lane-mask tables fit the staging
+                    assert c["items"] >= 2 ** c["radix_bits"] // 32
+                else:
+                    # two digits per thread; tile positions are 16-bit
+                    assert c["threads"] == 1024 and c["threads"] * c["items"] <= 1 << 16
     assert rs.configs(64, True)[0]["threads"] == 512  # registers of 16 u64 pairs per thread
     L = rs.lib()
     cnt = ctypes.c_int()
@@ -153,6 +161,12 @@ def test_tune_table(rs, ctx):
     # smaller tiles: more look-back words in the workspace
     assert ctx.workspace_bytes(32, True, 1 << 26) > w0
     assert ctx.workspace_bytes(32, True, 1 << 25) == ctx.workspace_bytes(32, True, 1 << 25)
+    wide = [i for i, c in enumerate(cfgs) if c["radix_bits"] == 11][0]
+    with pytest.raises(rs.RSError):
+        ctx.tune_set(32, True, True, -1, wide)  # the segmented sort has no wide digits
+    ctx.tune_set(32, True, False, 26, wide)
+    assert ctx.tune_get(32, True, False, 26) == wide
+    ctx.tune_set(32, True, False, 26, -1)
     r4 = [i for i, c in enumerate(cfgs) if c["radix_bits"] == 4][0]
     ctx.tune_set(32, True, True, -1, r4)
     for cls in (0, 17, 39):
