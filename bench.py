@@ -169,6 +169,9 @@ def parse():
                     help="segmented workload: number of segments")
     ap.add_argument("--seg-log2", default="4,20",
                     help="segmented workload: log2 of the smallest and largest segment size")
+    ap.add_argument("--seg-dist", default="uniform", choices=["uniform", "bucket", "zero"],
+                    help="segmented workload: key distribution (bucket: the same draws mapped "
+                         "through a table of 64 distinct values by their top 6 bits)")
     ap.add_argument("--tiny-cap", type=int, default=-1,
                     help="segmented workload: segments of 2..cap elements go to the bitonic "
                          "network (0: to the radix block sort; -1: the library default)")
@@ -220,7 +223,10 @@ def bench_serving(args, torch, rs, datagen, dev):
 
     def run(reqs, open_loop):
         be = HipBackend(slots=args.slots, keep_results=False)
-        sch = Scheduler(be, mem_cap=64 << 30, slots=args.slots, max_batch_elems=1 << 25)
+        # admission: each batch's real device bytes (staging, output, the
+        # library's workspace) under 64 GB or the free device memory
+        sch = Scheduler(be, mem_cap=be.admission_cap(64 << 30), slots=args.slots,
+                        max_batch_elems=1 << 25, batch_bytes=be.batch_bytes)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         be.mark_clock_zero(0.0)
@@ -235,7 +241,8 @@ def bench_serving(args, torch, rs, datagen, dev):
         st = summarize(done, makespan)
         st.update({"failed": len(sch.failed), "rejected": len(sch.rejected),
                    "peak_inflight_batches": sch.peak_inflight,
-                   "peak_admitted_GB": round(sch.peak_mem / 1e9, 2)})
+                   "peak_admitted_GB": round(sch.peak_mem / 1e9, 2),
+                   "admission_cap_GB": round(sch.mem_cap / 1e9, 2)})
         return st
 
     # warm-up on a few requests, then the closed loop for R_max
@@ -260,7 +267,8 @@ def bench_serving(args, torch, rs, datagen, dev):
         "dtype": "u32+u64", "data": "synthetic",
         "config": {"workload": f"{args.requests} Poisson-arriving sort requests, n = "
                                f"floor(2^({lo}+{hi - lo}u)), half u32 / half u64 keys, half "
-                               f"key-value; 64 GB admission cap; {args.slots} streams; "
+                               f"key-value; admission by each batch's device bytes under "
+                               f"min(64 GB, free HBM - 2 GiB); {args.slots} streams; "
                                f"rate 0.9 R_max", "requests": args.requests},
         "r_max_req_s": round(r_max, 1),
         "closed_loop": closed,
@@ -382,6 +390,12 @@ def measure_segmented(args, torch, rs, datagen, dev, with_cpu=True, quick=False)
     t0 = time.perf_counter()
     print(f"generating {S} segments on the host", file=sys.stderr, flush=True)
     keys, vals, off = datagen.segmented(num_segments=S, lo_log2=lo, hi_log2=hi, bits=32, seed=1)
+    if args.seg_dist == "zero":
+        keys[:] = 0
+    elif args.seg_dist == "bucket":
+        table = np.unique(datagen.MT19937(2).u32(256))[:64]
+        assert table.size == 64
+        keys = table[keys >> np.uint32(26)]
     gen_s = time.perf_counter() - t0
     print(f"generated {off[-1]} elements in {gen_s:.1f} s", file=sys.stderr, flush=True)
     total = int(off[-1])
@@ -536,7 +550,8 @@ def measure_segmented(args, torch, rs, datagen, dev, with_cpu=True, quick=False)
         "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"{S} independent u32 key + u32 value segments, sizes "
                                f"floor(2^({lo}+{hi - lo}u)) log-uniform in [2^{lo}, 2^{hi}], "
-                               f"uniform keys, value = index in segment; MT19937 seed 1",
+                               f"{args.seg_dist} keys, value = index in segment; MT19937 "
+                               f"seed 1",
                    "segments": S, "total_elements": total,
                    "elements_in_large_segments": int(large.sum()),
                    "tiny_cap": tiny_cap,

@@ -931,10 +931,14 @@ struct SegHistArgs {
     const uint32_t *chunk_seg;
     uint32_t max_chunks;
     uint32_t *ctrl;
-    uint32_t *seg_hist;  // [large segment][d][2^R], zeroed
-    uint32_t *seg_base;  // [large segment][d][2^R]
-    uint32_t kmap;       // key order applied to every key read
+    uint32_t *seg_hist;   // [large segment][d][2^R], zeroed
+    uint32_t *seg_base;   // [large segment][d][2^R]
+    uint32_t *seg_flags;  // [large segment]: bit p pass p's digit is the same for the
+                          // whole segment; bit 16 + p pass p's digits are skewed
+    uint32_t kmap;        // key order applied to every key read
 };
+
+constexpr int kSegSkewShift = 16;
 
 constexpr int kSegHistThreads = 1024;
 
@@ -1022,8 +1026,10 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegHistArgs a)
 {
     constexpr int D = num_passes<K, R>();
     constexpr int NB = 1 << R;
+    static_assert(D <= kSegSkewShift, "pass flags fit 16 bits each");
     __shared__ uint32_t s_tmp[8];
     __shared__ uint32_t s_item;
+    __shared__ unsigned long long s_sq[256 / kWave];
     const uint32_t t = threadIdx.x;
     while (true) {
         if (t == 0)
@@ -1032,13 +1038,34 @@ __global__ __launch_bounds__(256) void k_seg_scan(SegHistArgs a)
         const uint32_t item = s_item;
         if (item >= a.ctrl[kSegLargeLen])
             break;
+        const uint32_t size = a.large[item].size;
+        uint32_t flags = 0;
         for (int p = 0; p < D; ++p) {
             const uint64_t i = ((uint64_t)item * D + p) * NB + t;
             const uint32_t c = t < (uint32_t)NB ? a.seg_hist[i] : 0u;
             const uint32_t ex = bins_exclusive_scan<NB>(c, s_tmp);
             if (t < (uint32_t)NB)
                 a.seg_base[i] = ex;
+            // one digit for the whole segment: this pass is the identity
+            const bool trivial = __syncthreads_or(c == size) != 0;
+            // skewed: sum of squared counts above size^2 / 100 (as k_plan)
+            unsigned long long sq = (unsigned long long)c * c;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                sq += __shfl_xor(sq, off);
+            if ((t & (kWave - 1)) == 0)
+                s_sq[t / kWave] = sq;
+            __syncthreads();
+            unsigned long long tot = 0;
+#pragma unroll
+            for (int w = 0; w < 256 / kWave; ++w)
+                tot += s_sq[w];
+            const bool skewed = tot > (unsigned long long)size * size / 100ull;
+            flags |= (trivial ? 1u << p : 0u) | (skewed ? 1u << (kSegSkewShift + p) : 0u);
+            __syncthreads();
         }
+        if (t == 0)
+            a.seg_flags[item] = flags;
         __syncthreads();
     }
 }
@@ -1055,6 +1082,7 @@ struct SegPassArgs {
     const SegLarge *large;
     const uint32_t *tile_seg;
     const uint32_t *seg_base;  // [large segment][d][2^R]
+    const uint32_t *seg_flags; // [large segment]: trivial and skewed passes (k_seg_scan)
     uint32_t *ctrl;            // segmented control block
     uint32_t *status;          // look-back words of this pass
     uint32_t *claims;          // claim counters of this pass
@@ -1097,14 +1125,41 @@ __global__ __launch_bounds__(C::kThreads) void k_seg_pass(SegPassArgs a)
         const uint32_t lt = tile - rec.tile_start;
         const uint32_t first = lt * T;
         const uint32_t valid = rec.size > first ? std::min<uint32_t>(T, rec.size - first) : 0u;
-        const uint32_t dbase = t < NB ? a.seg_base[((uint64_t)seg * a.d + a.pass) * NB + t] : 0u;
+        const uint32_t flags = a.seg_flags[seg];
         const uint64_t off = rec.start + (uint64_t)lt * T;
+        if ((flags >> a.pass) & 1u) {
+            // the segment's digit is the same everywhere: the pass is the
+            // identity permutation, so the tile is copied (no rank, no
+            // look-back; the segment's other tiles do the same).  All of a
+            // thread's loads are in flight before its first store.
+            const uint32_t off0 = (t / kWave) * (kWave * C::kItems) + t % kWave;
+            K key[C::kItems];
+            V val[HAS_V ? C::kItems : 1];
+            load_tile<K, V, HAS_V, C::kItems>((const K *)a.src_k + off,
+                                              HAS_V ? (const V *)a.src_v + off : nullptr, valid,
+                                              off0, key, val, valid == (uint32_t)T, a.map_load);
+            K *dk = (K *)a.dst_k + off;
+            V *dv = HAS_V ? (V *)a.dst_v + off : nullptr;
+#pragma unroll
+            for (int j = 0; j < C::kItems; ++j) {
+                const uint32_t i = off0 + j * kWave;
+                if (i < valid) {
+                    dk[i] = map_out(key[j], a.map_store);
+                    if constexpr (HAS_V)
+                        dv[i] = val[j];
+                }
+            }
+            __syncthreads();  // every thread has read this tile's id
+            continue;
+        }
+        const uint32_t dbase = t < NB ? a.seg_base[((uint64_t)seg * a.d + a.pass) * NB + t] : 0u;
         pass_tile<K, V, HAS_V, C>(L, (const K *)a.src_k + off,
                                   HAS_V ? (const V *)a.src_v + off : nullptr,
                                   (K *)a.dst_k + rec.start,
                                   HAS_V ? (V *)a.dst_v + rec.start : nullptr, valid, rec.size,
-                                  tile, rec.tile_start, a.status, nullptr, dbase, a.shift, false,
-                                  a.map_load, a.map_store, pa, [](uint32_t) {});
+                                  tile, rec.tile_start, a.status, nullptr, dbase, a.shift,
+                                  ((flags >> (kSegSkewShift + a.pass)) & 1u) != 0, a.map_load,
+                                  a.map_store, pa, [](uint32_t) {});
     }
 }
 

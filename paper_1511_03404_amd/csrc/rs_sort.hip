@@ -696,7 +696,7 @@ struct SegLayout {
     uint64_t max_chunks;
     uint64_t off_ctrl, off_tiny, off_small, off_medium, off_large, off_base, off_tile_seg,
         off_status, status_bytes, off_tmp_k, off_tmp_v, total;
-    uint64_t off_hist, off_chunk_seg;
+    uint64_t off_hist, off_chunk_seg, off_flags;
 };
 
 static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total, uint32_t nseg,
@@ -722,6 +722,8 @@ static SegLayout make_seg_layout(int key_bytes, bool has_values, uint64_t total,
     o = align_up(o + (uint64_t)nseg * sizeof(SegLarge), 256);
     L.off_base = o;
     o = align_up(o + (uint64_t)nseg * L.d * L.bins * 4, 256);
+    L.off_flags = o;
+    o = align_up(o + (uint64_t)nseg * 4, 256);
     L.off_tile_seg = o;
     o = align_up(o + L.max_tiles * 4, 256);
     L.max_chunks = total / kSegChunk + nseg + 1;
@@ -799,6 +801,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     SegRange *medium_list = (SegRange *)(wb + L.off_medium);
     SegLarge *large = (SegLarge *)(wb + L.off_large);
     uint32_t *seg_base = (uint32_t *)(wb + L.off_base);
+    uint32_t *seg_flags = (uint32_t *)(wb + L.off_flags);
     uint32_t *tile_seg = (uint32_t *)(wb + L.off_tile_seg);
     uint32_t *chunk_seg = (uint32_t *)(wb + L.off_chunk_seg);
     uint32_t *seg_hist = (uint32_t *)(wb + L.off_hist);
@@ -865,8 +868,8 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
     // pass may not write its own input) with an odd d, the passes start in
     // the scratch copy and the large segments are copied back at the end.
     {
-        SegHistArgs ha{kin, large, chunk_seg, (uint32_t)L.max_chunks, ctrl, seg_hist, seg_base,
-                       kmap};
+        SegHistArgs ha{kin,      large,    chunk_seg, (uint32_t)L.max_chunks, ctrl,
+                       seg_hist, seg_base, seg_flags, kmap};
         const uint32_t g = std::min<uint64_t>(grid_of(op.hist_kernel, kSegHistThreads), L.max_chunks);
         launch(ctx, s, "k_seg_hist", [&] { op.hist(ha, g, s); });
         const uint32_t gs = std::min<uint32_t>(grid_of(op.scan_kernel, 256), nseg);
@@ -887,6 +890,7 @@ static rs_status run_segmented(rs_context *ctx, const void *kin, const void *vin
             pa.large = large;
             pa.tile_seg = tile_seg;
             pa.seg_base = seg_base;
+            pa.seg_flags = seg_flags;
             pa.ctrl = ctrl;
             pa.status = status + (uint64_t)p * L.max_tiles * L.bins;
             pa.claims = status + (uint64_t)L.d * L.max_tiles * L.bins + (uint64_t)p * L.claim_words;

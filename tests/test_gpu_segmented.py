@@ -212,3 +212,34 @@ def test_full_batch_20000_segments(rs, oracle_lib):
         ok, ov = oracle_lib.sort(keys[a:b], vals[a:b])
         assert np.array_equal(ko[a:b].cpu().numpy(), ok), f"segment {s}"
         assert np.array_equal(vo[a:b].cpu().numpy(), ov), f"segment {s}"
+
+
+@pytest.mark.parametrize("order,descending", [("unsigned", False), ("signed", True),
+                                              ("float", False)])
+@pytest.mark.parametrize("bits", [32, 64])
+def test_trivial_and_skewed_passes_per_segment(rs, oracle_lib, order, descending, bits):
+    """Large segments whose digits are the same for the whole segment at some
+    passes (copied, not ranked) beside skewed and uniform ones, in one
+    batch; with key orders, so the copy applies the order maps on the first
+    and last pass."""
+    n = 70001
+    dt = np.uint32 if bits == 32 else np.uint64
+    top = dt(bits - 8)
+    parts = [
+        datagen.keys("uniform", n, bits, seed=1),                  # every pass moves
+        datagen.keys("uniform", n, bits, seed=2) & dt(0xFF),       # only the lowest digit moves
+        datagen.keys("uniform", n, bits, seed=3) << top,           # only the top digit moves
+        np.full(n, 12345, dtype=dt),                               # no pass moves
+        datagen.keys("bucket", n, bits, seed=4),                   # skewed digits
+        (datagen.keys("uniform", n, bits, seed=5) & dt(0xFF00)),   # only the second digit moves
+    ]
+    keys = np.concatenate(parts)
+    off = np.arange(len(parts) + 1, dtype=np.uint64) * np.uint64(n)
+    vals = local_index(off, keys.size, bits)
+    print(f"case trivial/skewed segments bits={bits} order={order} desc={descending}", flush=True)
+    kd, vd = dev(keys), dev(vals)
+    ko, vo = rs.segmented_sort(kd, vd, dev(off.view(np.int64)), order=order,
+                               descending=descending)
+    torch.cuda.synchronize()
+    ok, ov = oracle_lib.segmented_sort_ordered(keys, vals, off, order, descending)
+    assert np.array_equal(ko.cpu().numpy(), ok) and np.array_equal(vo.cpu().numpy(), ov)
