@@ -367,6 +367,16 @@ rs_status rs_tune_get(const rs_context *ctx, rs_key_type key_type, int has_value
  * Unsigned ascending order; otherwise as rs_sort.
  */
 rs_status rs_debug_wait_set(rs_context *ctx, uint32_t spin_limit, uint32_t stall);
+
+/*
+ * Measurement helper: a plain device copy of `bytes` bytes (a multiple of 16,
+ * both pointers 16-byte aligned, no overlap), each thread keeping its loads
+ * in flight before its stores.  The digit pass reads and writes every
+ * element once, so this copy's rate is the ceiling it is compared with.
+ * Asynchronous on `stream`; profiled like the sorts (kernel k_copy_ceiling).
+ */
+rs_status rs_device_copy(rs_context *ctx, const void *src, void *dst, uint64_t bytes,
+                         void *stream);
 rs_status rs_debug_sort_stages(rs_context *ctx, rs_key_type key_type, const void *keys_in,
                                const void *vals_in, void *keys_out, void *vals_out, uint64_t n,
                                int passes, uint32_t *hist_out, void *ws, size_t ws_bytes,

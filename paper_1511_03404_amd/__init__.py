@@ -50,6 +50,7 @@ EXPORTED = (
     "rs_segmented_tiny_cap_set", "rs_segmented_tiny_cap_get",
     "rs_workspace_status", "rs_debug_wait_set", "rs_debug_sort_stages",
     "rs_sort_noalloc", "rs_sort_noalloc_scratch_bytes", "rs_segmented_config_count",
+    "rs_device_copy",
 )
 
 
@@ -105,6 +106,8 @@ def lib():
             L.rs_config_count.argtypes = [ci, ci, ctypes.POINTER(ci)]
             L.rs_segmented_config_count.argtypes = [ci, ci, ctypes.POINTER(ci)]
             L.rs_segmented_config_count.restype = ci
+            L.rs_device_copy.argtypes = [vp, vp, vp, u64, vp]
+            L.rs_device_copy.restype = ci
             L.rs_config_get.argtypes = [ci, ci, ci, ctypes.POINTER(Config)]
             L.rs_tune_set.argtypes = [vp, ci, ci, ci, ci, ci]
             L.rs_tune_get.argtypes = [vp, ci, ci, ci, ci, ctypes.POINTER(ci)]
@@ -476,3 +479,16 @@ def sort_stages(keys: torch.Tensor, values: torch.Tensor | None = None, passes: 
                                       _ptr(vo), n, int(passes), _ptr(hist), _ptr(ws), ws.numel(),
                                       _stream(ctx.device)))
     return hist, ko, vo
+
+
+def device_copy(src: torch.Tensor, dst: torch.Tensor, *, ctx: Context | None = None):
+    """Measurement helper: the library's plain copy of src into dst (device
+    tensors of the same byte size, a multiple of 16)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("contiguous device tensors required")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same byte size")
+    ctx = ctx or context(src.device.index)
+    _check(lib().rs_device_copy(ctx.handle, _ptr(src), _ptr(dst), nbytes, _stream(ctx.device)))
+    return dst

@@ -324,3 +324,16 @@ def test_noalloc_rejects_what_its_scratch_cannot_hold(rs, ctx):
     assert L.rs_sort_noalloc(None, 0, 0, fake, None, fake, None, 10,
                              None) == rs.RS_ERR_INVALID_ARGUMENT
     assert L.rs_sort_noalloc(ctx.handle, 0, 0, None, None, None, None, 0, None) == rs.RS_OK
+
+
+def test_device_copy_validates_on_the_host(rs, ctx):
+    L = rs.lib()
+    fake = 0x7F0000000000
+    assert L.rs_device_copy(ctx.handle, None, None, 0, None) == rs.RS_OK
+    assert L.rs_device_copy(None, fake, fake + (1 << 20), 16, None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_device_copy(ctx.handle, fake, fake + (1 << 20), 24, None) == \
+        rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_device_copy(ctx.handle, fake + 8, fake + (1 << 20), 16, None) == \
+        rs.RS_ERR_INVALID_ARGUMENT
+    assert L.rs_device_copy(ctx.handle, fake, fake + 64, 128, None) == rs.RS_ERR_INVALID_ARGUMENT
+    assert b"overlap" in L.rs_last_error()

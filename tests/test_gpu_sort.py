@@ -239,3 +239,15 @@ def test_device_status_is_ok_after_a_sort(rs, bits, pairs):
             rs._check(f(ctx.handle, rs._ptr(keys), rs._ptr(vals), rs._ptr(ko), rs._ptr(vo), n,
                         None, 0, rs._stream(0)))
             assert ctx.status(None) == rs.RS_OK
+
+
+def test_device_copy_is_exact(rs):
+    """The copy that measures the bench's copy ceiling copies exactly,
+    including sizes that leave the last workgroup partly idle."""
+    for nbytes in (16, 4096 * 16 + 48, (1 << 26) + 16 * 7):
+        src = torch.randint(-(1 << 31), 1 << 31, (nbytes // 4,), dtype=torch.int64,
+                            device="cuda").to(torch.int32)
+        dst = torch.zeros_like(src)
+        rs.device_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), nbytes
