@@ -782,8 +782,8 @@ def main():
         print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                          "a design note, not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the sort runs on one GPU only; sharding across GPUs is "
+                          "described in the design notes, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
