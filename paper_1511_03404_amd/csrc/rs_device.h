@@ -196,21 +196,26 @@ __device__ __forceinline__ uint64_t peer_mask(uint32_t d)
     return ~(((uint64_t)diff_hi << 32) | diff_lo);
 }
 
-__device__ __forceinline__ uint32_t shfl_idx(uint32_t v, uint32_t src_lane)
+// Lane i of each 16-lane row takes lane i - n of its row, 0 where that
+// lane does not exist (DPP row shift, VALU latency, no LDS round trip).
+template <int N>
+__device__ __forceinline__ uint32_t row_shr(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src_lane << 2), (int)v);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + N, 0xf, 0xf, false);
 }
 
-// Inclusive scan across the 64 lanes of a wave.
+// Inclusive scan across the 64 lanes of a wave, with DPP: shifts by 1, 2,
+// 4 and 8 lanes make each 16-lane row an inclusive scan; then row 0's last
+// lane is added into row 1 and row 2's into row 3 (row_bcast:15), and lane
+// 31 (the total of rows 0-1) into rows 2 and 3 (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v)
 {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        uint32_t o = shfl_idx(v, lane >= (uint32_t)off ? lane - off : lane);
-        if (lane >= (uint32_t)off)
-            v += o;
-    }
+    v += row_shr<1>(v);
+    v += row_shr<2>(v);
+    v += row_shr<4>(v);
+    v += row_shr<8>(v);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
     return v;
 }
 

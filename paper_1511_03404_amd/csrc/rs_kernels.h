@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// k_plan (one workgroup of 256 threads): digit_base = exclusive scan of each
+// k_plan (one workgroup, 256 threads per row group): digit_base = exclusive scan of each
 // histogram row (the counting sort's starting offsets), and the plan of
 // every pass.  A pass whose digit is the same for all n keys is the identity
 // permutation and is skipped; the remaining passes alternate between the
@@ -228,60 +228,85 @@ struct PlanArgs {
     int limit;          // digit positions [0, limit) are sorted (the whole key: d)
 };
 
+// Rows are scanned side by side: row group g (threads [256 g, 256 g + 256))
+// takes rows g, g + G, g + 2 G, ... (G = plan_groups row groups); a group's
+// 256 threads hold up to 256 bins one each, wide digits several consecutive
+// bins per thread.
 template <typename K, int R>
-__global__ __launch_bounds__(kRadix) void k_plan(PlanArgs a)
+constexpr int plan_groups()
+{
+    return num_passes<K, R>() < 4 ? num_passes<K, R>() : 4;
+}
+
+template <typename K, int R>
+__global__ __launch_bounds__(kRadix * 4) void k_plan(PlanArgs a)
 {
     constexpr int D = num_passes<K, R>();
     constexpr int NB = 1 << R;
-    // bins per thread: up to 256 bins one each, wide digits several
-    // consecutive bins per thread
+    constexpr int G = plan_groups<K, R>();
+    constexpr int ROUNDS = (D + G - 1) / G;
     constexpr int BPT = NB > kRadix ? NB / kRadix : 1;
-    constexpr int SCAN = NB > kRadix ? kRadix : NB;
-    __shared__ uint32_t s_tmp[8];
+    constexpr int WPG = kRadix / kWave;  // waves per group
+    __shared__ uint32_t s_tot[G][WPG];
+    __shared__ unsigned long long s_sq[G][WPG];
     __shared__ int s_trivial[D];
     __shared__ int s_skewed[D];
-    __shared__ unsigned long long s_sq[kRadix / kWave];
     const uint32_t t = threadIdx.x;
-    const bool active = t * BPT < (uint32_t)NB;
+    const uint32_t g = t / kRadix;
+    const uint32_t lt = t % kRadix;
+    const uint32_t w = lt / kWave;
+    const bool active = lt * BPT < (uint32_t)NB;
+    if (t < (uint32_t)D)
+        s_trivial[t] = 0;
     // every row's load in flight at once, not one latency per digit position
-    uint32_t cnt[D][BPT];
+    uint32_t cnt[ROUNDS][BPT];
 #pragma unroll
-    for (int p = 0; p < D; ++p)
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int p = r * G + (int)g;
 #pragma unroll
         for (int i = 0; i < BPT; ++i)
-            cnt[p][i] = active ? a.hist[p * NB + t * BPT + i] : 0u;
+            cnt[r][i] = (active && p < D) ? a.hist[p * NB + lt * BPT + i] : 0u;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int p = 0; p < D; ++p) {
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int p = r * G + (int)g;
         uint32_t sum = 0;
         bool full = false;
         unsigned long long sq = 0;
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {
-            sum += cnt[p][i];
-            full = full || cnt[p][i] == a.n;
-            sq += (unsigned long long)cnt[p][i] * cnt[p][i];
+            sum += cnt[r][i];
+            full = full || cnt[r][i] == a.n;
+            sq += (unsigned long long)cnt[r][i] * cnt[r][i];
         }
-        uint32_t ex = bins_exclusive_scan<SCAN>(sum, s_tmp);
-        if (active) {
-#pragma unroll
-            for (int i = 0; i < BPT; ++i) {
-                a.digit_base[p * NB + t * BPT + i] = ex;
-                ex += cnt[p][i];
-            }
-        }
-        const int triv = __syncthreads_or(full);
+        // exclusive scan of the row over the group's threads
+        const uint32_t inc = wave_inclusive_scan(sum);
         // chance that two keys share this digit: sum_b (c_b / n)^2
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
             sq += __shfl_xor(sq, off);
-        if ((t & (kWave - 1)) == 0)
-            s_sq[t / kWave] = sq;
+        if ((lt & (kWave - 1)) == kWave - 1)
+            s_tot[g][w] = inc;
+        if ((lt & (kWave - 1)) == 0)
+            s_sq[g][w] = sq;
+        if (full && p < D)
+            s_trivial[p] = 1;  // every writer stores the same value
         __syncthreads();
-        if (t == 0) {
-            s_trivial[p] = triv;
+        uint32_t ex = inc - sum;
+        for (uint32_t i = 0; i < w; ++i)
+            ex += s_tot[g][i];
+        if (active && p < D) {
+#pragma unroll
+            for (int i = 0; i < BPT; ++i) {
+                a.digit_base[p * NB + lt * BPT + i] = ex;
+                ex += cnt[r][i];
+            }
+        }
+        if (lt == 0 && p < D) {
             unsigned long long tot = 0;
-            for (int i = 0; i < kRadix / kWave; ++i)
-                tot += s_sq[i];
+            for (int i = 0; i < WPG; ++i)
+                tot += s_sq[g][i];
             // above 1/100 many lanes of a wave share a slot of the LDS lane-mask
             // table, whose same-address atomics serialise; ballots do not
             // (n < 2^30, so n^2 fits 64 bits; tot <= n^2)

@@ -44,7 +44,7 @@ struct SortLaunch {
     }
     static void plan(const PlanArgs &a, hipStream_t s)
     {
-        hipLaunchKernelGGL((k_plan<K, R>), dim3(1), dim3(kRadix), 0, s, a);
+        hipLaunchKernelGGL((k_plan<K, R>), dim3(1), dim3(kRadix * plan_groups<K, R>()), 0, s, a);
     }
     static void pass(const PassArgs &a, uint32_t grid, hipStream_t s)
     {
