@@ -4,13 +4,14 @@
 // Method (paper, Section 2.6): d = ceil(K/R) passes of R-bit digits, least
 // significant first, each a stable counting sort.  The GPU realisation:
 //
-//   k_hist     one read of the keys -> histograms of all d digit positions;
-//              also clears the look-back words of every pass
-//   k_plan     one workgroup: scans each histogram row into digit_base (the
-//              counting sort's exclusive prefix sums) and writes a plan:
-//              which passes move data (a pass whose histogram has a single
-//              non-empty digit is the identity and is skipped) and which
-//              buffer each pass reads and writes
+//   k_hist     one read of the keys -> histograms of all d digit positions
+//              (added into one histogram, or for small sorts one row block
+//              per workgroup); also clears the look-back words of every pass
+//   k_plan     one workgroup: sums the row blocks if any, scans each
+//              histogram row into digit_base (the counting sort's exclusive
+//              prefix sums) and writes a plan: which passes move data (a pass
+//              whose histogram has a single non-empty digit is the identity
+//              and is skipped) and which buffer each pass reads and writes
 //   k_pass     one per digit position: a single sweep over the data that
 //              counts, scans (decoupled look-back across tiles) and places
 //              each tile; see rs_device.h.
@@ -92,7 +93,9 @@ struct HistArgs {
     uint32_t n;
     uint32_t head;        // leading keys before the first 16-byte boundary
     uint32_t nvec;        // 16-byte vectors after the head
-    uint32_t *hist;       // [d][2^R]
+    uint32_t *hist;       // [d][2^R], accumulated with atomics (cleared before)
+    uint32_t *part;       // or, when not null: [grid][d][2^R], one row block per
+                          // workgroup, plain stores (nothing to clear first)
     uint4 *status;        // look-back words of all passes, cleared here
     uint64_t status_vec;  // number of uint4 in status
     uint32_t kmap;        // key order (kMap*), applied to every key read
@@ -137,6 +140,25 @@ __device__ __forceinline__ void hist_flush(const uint32_t *tab, uint32_t *hist, 
             atomicAdd(&hist[r], s);
     }
 }
+
+// Stores this workgroup's counters as its own row block of part ([d][2^R]),
+// zero rows included.
+template <int D, int R, int COLS = kHistCols>
+__device__ __forceinline__ void hist_store(const uint32_t *tab, uint32_t *part, uint32_t t)
+{
+    for (uint32_t r = t; r < (uint32_t)D << R; r += kHistThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (uint32_t c = 0; c < COLS; ++c)
+            s += tab[r * COLS + ((c + r) & (COLS - 1))];
+        part[r] = s;
+    }
+}
+
+// Up to this many k_hist workgroups (small sorts) write row blocks that
+// k_plan sums, instead of adding into a histogram cleared by a launch of its
+// own; beyond it the sum would cost k_plan more than that launch.
+constexpr uint32_t kHistPartsMax = 16;
 
 template <typename K, int R>
 __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
@@ -208,7 +230,10 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
             hist_add<R, COLS>(tab, p, digit_of<R>(key, p * R), col);
     }
     __syncthreads();
-    hist_flush<D, R, COLS>(tab, a.hist, t);
+    if (a.part)
+        hist_store<D, R, COLS>(tab, a.part + (uint64_t)blockIdx.x * ((uint32_t)D << R), t);
+    else
+        hist_flush<D, R, COLS>(tab, a.hist, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,7 +244,9 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
 // output and the scratch copy so that the last one lands in the output.
 
 struct PlanArgs {
-    const uint32_t *hist;
+    uint32_t *hist;         // [d][2^R]: read; or written, as the sum of part
+    const uint32_t *part;   // k_hist's row blocks ([parts][d][2^R]) when parts > 0
+    uint32_t parts;
     uint32_t *digit_base;
     uint32_t *ctrl;
     uint32_t n;
@@ -258,6 +285,10 @@ __global__ __launch_bounds__(kRadix * 4) void k_plan(PlanArgs a)
     const bool active = lt * BPT < (uint32_t)NB;
     if (t < (uint32_t)D)
         s_trivial[t] = 0;
+    // the control block starts cleared (claim counters, error word); the
+    // plan words are written at the end, after barriers
+    for (uint32_t i = t; i < (uint32_t)kCtrlWords; i += blockDim.x)
+        a.ctrl[i] = 0;
     // every row's load in flight at once, not one latency per digit position
     uint32_t cnt[ROUNDS][BPT];
 #pragma unroll
@@ -265,7 +296,46 @@ __global__ __launch_bounds__(kRadix * 4) void k_plan(PlanArgs a)
         const int p = r * G + (int)g;
 #pragma unroll
         for (int i = 0; i < BPT; ++i)
-            cnt[r][i] = (active && p < D) ? a.hist[p * NB + lt * BPT + i] : 0u;
+            cnt[r][i] = (active && p < D && !a.parts) ? a.hist[p * NB + lt * BPT + i] : 0u;
+    }
+    if (a.parts) {
+        // sum the row blocks of k_hist's workgroups, 8 blocks' loads in
+        // flight at once (unconditional loads of in-range words, masked
+        // after); hist then holds the sum
+        constexpr uint32_t CHUNK = 8;
+        for (uint32_t b0 = 0; b0 < a.parts; b0 += CHUNK) {
+            uint32_t v[CHUNK][ROUNDS][BPT];
+#pragma unroll
+            for (uint32_t j = 0; j < CHUNK; ++j) {
+                const uint32_t b = min(b0 + j, a.parts - 1);
+                const uint32_t *pb = a.part + (uint64_t)b * (D * NB);
+#pragma unroll
+                for (int r = 0; r < ROUNDS; ++r) {
+                    const int p = min(r * G + (int)g, D - 1);
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i)
+                        v[j][r][i] = pb[p * NB + min(lt * BPT + i, (uint32_t)NB - 1)];
+                }
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < CHUNK; ++j) {
+#pragma unroll
+                for (int r = 0; r < ROUNDS; ++r) {
+                    const bool use = b0 + j < a.parts && active && r * G + (int)g < D;
+#pragma unroll
+                    for (int i = 0; i < BPT; ++i)
+                        cnt[r][i] += use ? v[j][r][i] : 0u;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < ROUNDS; ++r) {
+            const int p = r * G + (int)g;
+#pragma unroll
+            for (int i = 0; i < BPT; ++i)
+                if (active && p < D)
+                    a.hist[p * NB + lt * BPT + i] = cnt[r][i];
+        }
     }
     __syncthreads();
 #pragma unroll

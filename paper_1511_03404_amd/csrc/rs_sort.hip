@@ -5,7 +5,8 @@
 // rs_var_*.hip units; the one-workgroup LDS sort is in rs_block.h.
 //
 // A plain sort of n elements, n above the one-workgroup limit:
-//   k_init      zero the control block and the digit histograms
+//   k_init      zero the control block and the digit histograms (sorts whose
+//               k_hist adds into one histogram; small sorts skip it)
 //   k_hist      all digit histograms in one read; clears the look-back words
 //   k_plan      digit_base scans, skipped passes, buffer ping-pong
 //   k_pass x d  one sweep per digit
@@ -270,7 +271,9 @@ struct Layout {
     uint32_t bins;  // 2^r
     uint32_t tile;
     uint64_t tiles;
-    uint64_t off_ctrl, off_hist, off_base, off_status, off_tmp_k, off_tmp_v, total;
+    uint64_t off_ctrl, off_hist, off_base, off_part, off_status, off_tmp_k, off_tmp_v, total;
+    uint32_t hist_blocks;   // workgroups of k_hist
+    uint32_t parts;         // hist_blocks if k_hist writes row blocks, else 0
     uint64_t status_bytes;  // look-back words, claim counters, group aggregates of all passes
     uint64_t claim_words;
     uint64_t groups;        // tile groups of the two-level look-back
@@ -290,6 +293,10 @@ static Layout make_layout(int key_bytes, bool has_values, uint64_t n, const Sort
     o = align_up(o + (uint64_t)L.d * L.bins * 4, 256);
     L.off_base = o;
     o = align_up(o + (uint64_t)L.d * L.bins * 4, 256);
+    L.hist_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(512, (n + 16383) / 16384));
+    L.parts = L.hist_blocks <= kHistPartsMax ? L.hist_blocks : 0u;
+    L.off_part = o;
+    o = align_up(o + (uint64_t)L.parts * L.d * L.bins * 4, 256);
     L.off_status = o;
     L.claim_words = kXcdSlots * (1 + L.tiles);  // per-XCD counters + per-XCD group lists
     L.groups = (L.tiles + kClaimGroup - 1) / kClaimGroup;
@@ -538,9 +545,12 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
 
     Bufs b{kin, vin, kout, vout, wb + L.off_tmp_k, HAS_V ? (void *)(wb + L.off_tmp_v) : nullptr};
 
-    launch(ctx, s, "k_init", [&] {
-        hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, ctrl, hist, (int)(L.d * L.bins));
-    });
+    // the histogram that k_hist adds into starts cleared; with row blocks
+    // (small sorts) nothing needs clearing (k_plan clears the control block)
+    if (!L.parts)
+        launch(ctx, s, "k_init", [&] {
+            hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, s, ctrl, hist, (int)(L.d * L.bins));
+        });
 
     HistArgs ha{};
     ha.keys = kin;
@@ -552,17 +562,19 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     ha.kmap = kmap;
     ha.status = (uint4 *)status;
     ha.status_vec = L.status_bytes / 16;
-    const uint64_t hist_blocks = std::max<uint64_t>(
-        1, std::min<uint64_t>(512, (n + 16383) / 16384));
+    uint32_t *part = (uint32_t *)(wb + L.off_part);
+    ha.part = L.parts ? part : nullptr;
     launch(ctx, s, sizeof(K) == 4 ? "k_hist_u32" : "k_hist_u64",
-           [&] { op.hist(ha, (uint32_t)hist_blocks, s); });
+           [&] { op.hist(ha, L.hist_blocks, s); });
+
+    PlanArgs pl{hist, part, L.parts, base, ctrl, (uint32_t)n, keys_in_place, vals_in_place,
+                run_passes};
+    launch(ctx, s, "k_plan", [&] { op.plan(pl, s); });
+    // after k_plan: with row blocks, k_plan writes their sum into hist
     if (hist_out &&
         hipMemcpyAsync(hist_out, hist, (size_t)L.d * L.bins * 4, hipMemcpyDeviceToDevice, s) !=
             hipSuccess)
         return fail(RS_ERR_DEVICE, "histogram copy failed");
-
-    PlanArgs pl{hist, base, ctrl, (uint32_t)n, keys_in_place, vals_in_place, run_passes};
-    launch(ctx, s, "k_plan", [&] { op.plan(pl, s); });
 
     // workgroups loop over claimed tiles: launch only what fits on the device
     // at once (more would start at the end just to find no work).  Tiles are
