@@ -62,3 +62,34 @@ def test_histograms_and_each_pass(rs, oracle_lib, bits, pairs, index, dist):
         if pairs:
             assert np.array_equal(vo.cpu().numpy(), sv), f"values differ after {p} passes"
     ctx.close()
+
+
+@pytest.mark.parametrize("dist", ["uniform", "bucket"])
+@pytest.mark.parametrize("n", [16 * 16384, 16 * 16384 + 1])
+@pytest.mark.parametrize("bits,pairs", KINDS)
+def test_histogram_modes(rs, oracle_lib, bits, pairs, n, dist):
+    """Both ways of building the histograms: up to 16 histogram workgroups
+    (one per 16384 keys) each write a row block that the plan kernel sums;
+    from 17 on they add into one cleared histogram.  Either way the
+    histograms and every pass equal the oracle's."""
+    ctx = rs.Context(0)
+    ctx.tune_set(bits, pairs, False, -1, 0)
+    cfg = rs.configs(bits, pairs)[0]
+    r = cfg["radix_bits"]
+    d = (bits + r - 1) // r
+    print(f"case bits={bits} pairs={pairs} n={n} dist={dist}", flush=True)
+    keys = datagen.keys(dist, n, bits, seed=n % 7 + 1)
+    vals = datagen.values(n, bits) if pairs else None
+    kd = dev(keys)
+    vd = dev(vals) if pairs else None
+    want_h = oracle_lib.digit_histograms(keys, r)
+    for p in (0, 1, d):
+        hist, ko, vo = rs.sort_stages(kd, vd, passes=p, ctx=ctx)
+        torch.cuda.synchronize()
+        assert ctx.status(None) == rs.RS_OK
+        assert np.array_equal(hist.cpu().numpy().astype(np.uint64), want_h), "histograms differ"
+        sk, sv = oracle_lib.sort(keys, vals, r=r, passes=p)
+        assert np.array_equal(ko.cpu().numpy(), sk), f"keys differ after {p} passes"
+        if pairs:
+            assert np.array_equal(vo.cpu().numpy(), sv), f"values differ after {p} passes"
+    ctx.close()
