@@ -30,6 +30,9 @@ namespace rs {
 
 // Consecutive tiles claimed as a group (see claim_tile).
 constexpr int kClaimGroup = 8;
+// Passes of at most this many tiles claim them in arrival order (see
+// claim_tile).
+constexpr uint32_t kFlatClaimTiles = 32;
 
 // Per-XCD claim counters (XCC_ID has 3 bits; gfx950 has 8 XCDs).
 constexpr uint32_t kXcdSlots = 8;
@@ -436,6 +439,7 @@ struct PassArgs {
     uint32_t *claims;            // per-XCD claim counters and group lists
     uint32_t num_tiles;
     uint32_t num_groups;
+    uint32_t flat;  // claim tiles from one counter in arrival order (few tiles)
     uint32_t kmap;  // key order (kMap*), 0 = unsigned ascending
     uint32_t *err;        // error word of the control block (kErrWait)
     uint32_t spin_limit;  // polls without progress before a wait gives up
@@ -478,11 +482,18 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 // Both waits are bounded: after a.spin_limit polls the claim records
 // kErrWait and returns kNoTile (an opener that gives up still publishes
 // kNoTile for its group, so nobody waits on it).
+//
+// A pass of few tiles (a.flat) takes them from the global counter in
+// arrival order instead: one atomic before the first load rather than the
+// opener's two and the wait for its group id, which is most of a small
+// pass's start; the partly shared lines of so few tiles cost less.  Arrival
+// order keeps the property above: every tile below a claimed one is held by
+// a running workgroup.
 template <int GROUP>
 __device__ __forceinline__ uint32_t claim_tile(const PassArgs &a, uint32_t xcc)
 {
     uint32_t *ctr = &a.ctrl[kCtrlTileCounter + a.pass];
-    if constexpr (GROUP == 1) {
+    if (GROUP == 1 || a.flat) {
         (void)xcc;
         const uint32_t t = atomicAdd(ctr, 1u);
         return t < a.num_tiles ? t : kNoTile;

@@ -581,9 +581,12 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     // claimed in groups per XCD and workgroups are dealt to the XCDs in turn,
     // so a small sort launches up to one workgroup per tile on every XCD:
     // otherwise an XCD holding a group could have fewer workgroups than tiles
-    // and process them one after another.
+    // and process them one after another.  A pass of few tiles claims them
+    // in arrival order: one workgroup per tile.
+    const bool flat = L.tiles <= kFlatClaimTiles;
     const uint32_t pass_grid = (uint32_t)std::min<uint64_t>(
-        L.tiles * kXcdSlots, (uint64_t)resident_blocks(op.pass_kernel, op.threads) * ctx_cus(ctx));
+        flat ? L.tiles : L.tiles * kXcdSlots,
+        (uint64_t)resident_blocks(op.pass_kernel, op.threads) * ctx_cus(ctx));
     // the passes of digit positions [0, run_passes); at least one is launched,
     // which copies the input when no pass moves data
     for (int p = 0; p < std::max(run_passes, 1); ++p) {
@@ -600,6 +603,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
                   (uint64_t)p * L.groups * L.bins;
         pa.num_tiles = (uint32_t)L.tiles;
         pa.num_groups = (uint32_t)((L.tiles + kClaimGroup - 1) / kClaimGroup);
+        pa.flat = flat ? 1u : 0u;
         pa.kmap = kmap;
         pa.err = ctrl + kCtrlError;
         pa.spin_limit = ctx->spin_limit;
