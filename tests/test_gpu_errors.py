@@ -34,9 +34,9 @@ def dev(a):
 @pytest.mark.parametrize("stall", [1, 2], ids=["lookback", "claim"])
 @pytest.mark.parametrize("bits", [32, 64])
 def test_bounded_waits_give_up_and_report(rs, oracle_lib, stall, bits):
-    # a pass of up to 32 tiles claims them in arrival order, with no wait:
-    # the claim case needs more tiles (48 of 16384 keys, or 96 of 8192)
-    n = (5 if stall == 1 else 48) * TILE + 3
+    # a pass of up to 1024 tiles claims them in arrival order, with no
+    # wait: the claim case needs more tiles (1100 of 16384 keys)
+    n = (5 if stall == 1 else 1100) * TILE + 3
     print(f"case stall={stall} bits={bits} n={n}", flush=True)
     keys = datagen.keys("uniform", n, bits, seed=3)
     vals = datagen.values(n, bits)
