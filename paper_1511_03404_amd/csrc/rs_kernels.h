@@ -488,7 +488,8 @@ constexpr uint32_t kNoTile = 0xFFFFFFFFu;
 // counter in arrival order instead: one atomic per claim rather than the
 // opener's two and the others' wait for the group id, and no group opening
 // in order.  Up to that size this costs less than the partly shared lines
-// it leaves between XCDs; at 4096 tiles (2^26 keys) the groups pay.
+// it leaves between XCDs; at 2048-4096 tiles (2^25-2^26 keys) the groups
+// pay, except for 32-bit keys without values.
 // Arrival order keeps the property above: every tile below a claimed one is
 // held by a running workgroup.
 template <int GROUP>
