@@ -28,10 +28,12 @@
     X(8, 1024, 8) X(8, 256, 16) X(8, 512, 8) X(8, 256, 32)
 
 // The plain sort also has wide digits (11 bits, the layout of rs_wide.h):
-// three passes for 32-bit keys, six for 64-bit keys.  They follow the
-// segmented lists, so an index below the segmented list's length names the
-// same configuration in both.
-#define RS_CONFIGS_U32_KEYS(X) RS_SEG_CONFIGS_U32_KEYS(X) X(11, 1024, 16)
+// three passes for 32-bit keys, six for 64-bit keys; and for 32-bit keys
+// alone, whose 16384-key tiles use 64 KB of staging, tiles of 24576 keys
+// (the built-in choice from 2^26 keys).  They follow the segmented lists,
+// so an index below the segmented list's length names the same
+// configuration in both.
+#define RS_CONFIGS_U32_KEYS(X) RS_SEG_CONFIGS_U32_KEYS(X) X(11, 1024, 16) X(8, 1024, 24)
 #define RS_CONFIGS_U32_PAIRS(X) RS_SEG_CONFIGS_U32_PAIRS(X) X(11, 1024, 16)
 #define RS_CONFIGS_U64_KEYS(X) RS_SEG_CONFIGS_U64_KEYS(X) X(11, 1024, 16)
 #define RS_CONFIGS_U64_PAIRS(X) RS_SEG_CONFIGS_U64_PAIRS(X) X(11, 1024, 8)

@@ -155,7 +155,9 @@ def test_tune_table(rs, ctx):
     assert ctx.tune_get(32, True, False, 26) == small
     assert ctx.tune_get(32, True, False, 25) == 0
     assert ctx.tune_get(32, True, True, 26) == 0
-    assert ctx.tune_get(32, False, False, 26) == 0
+    assert ctx.tune_get(32, False, False, 25) == 0
+    c32k = rs.configs(32, False)[ctx.tune_get(32, False, False, 26)]
+    assert (c32k["threads"], c32k["items"], c32k["radix_bits"]) == (1024, 24, 8)
     c64p = rs.configs(64, True)[ctx.tune_get(64, True, False, 26)]
     assert (c64p["threads"], c64p["items"]) == (1024, 8)
     # smaller tiles: more look-back words in the workspace
@@ -175,7 +177,8 @@ def test_tune_table(rs, ctx):
     assert ctx.tune_get(32, True, True, 17) == 0
     ctx.tune_set(32, True, False, 26, -1)
     # built-in choices of unset plain-sort classes: 1024 x 8 tiles up to 2^21
-    # (from 2^18 up for 64-bit pairs), the list's default above
+    # (from 2^18 up for 64-bit pairs), the list's default above (32-bit keys
+    # alone: 1024 x 24 from 2^26 on)
     for bits, pairs in ((32, False), (32, True), (64, False), (64, True)):
         c = rs.configs(bits, pairs)
         big = 39 if (bits, pairs) == (64, True) else 21
@@ -184,6 +187,10 @@ def test_tune_table(rs, ctx):
             assert (c[i]["threads"], c[i]["items"], c[i]["radix_bits"]) == (1024, 8, 8), (bits, pairs, cls)
         if big < 39:
             assert ctx.tune_get(bits, pairs, False, big + 1) == 0
+        if (bits, pairs) == (32, False):
+            for cls in (26, 30, 39):
+                i = ctx.tune_get(bits, pairs, False, cls)
+                assert (c[i]["threads"], c[i]["items"]) == (1024, 24), cls
         assert ctx.tune_get(bits, pairs, True, 17) == 0
     assert ctx.workspace_bytes(32, True, 1 << 26) == w0
     L = rs.lib()

@@ -102,6 +102,19 @@ def test_full_size_u32_pairs(rs, oracle_lib, dist):
     assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
 
 
+@pytest.mark.parametrize("dist,n", [("uniform", 1 << 26), ("bucket", 1 << 26),
+                                    ("gaussian", (1 << 26) + 12345), ("zero", 1 << 26)])
+def test_full_size_u32_keys(rs, oracle_lib, dist, n):
+    """32-bit keys alone from 2^26 on: tiles of 1024 x 24 claimed in arrival
+    order (the built-in choice there), against the oracle."""
+    print(f"case u32 keys n={n} dist={dist}", flush=True)
+    keys = datagen.keys(dist, n, 32, seed=2)
+    gk, _ = gpu_sort(rs, keys)
+    assert certify_sorted_keys(keys, gk) is None
+    ok, _ = oracle_lib.sort(keys)
+    assert np.array_equal(gk, ok)
+
+
 @pytest.mark.parametrize("pairs", [False, True])
 @pytest.mark.parametrize("dist", datagen.DISTRIBUTIONS)
 def test_full_size_u64(rs, oracle_lib, pairs, dist):
