@@ -167,10 +167,10 @@ static const SegOps *seg_table(int key_bytes, bool has_values, int *count)
 // table unless set otherwise).
 // The configuration a size class gets when its table entry is unset: what
 // the autotuner selected on MI355X for plain sorts of uniform keys.  Tiles
-// of 8192 elements (1024 x 8) up to 2^21 elements (2^24 for 64-bit pairs):
-// a small sort has few tiles, and a tile's latency, not HBM, sets the pass
-// time; tiles of 4096 at the smallest sizes of some kinds; the list's
-// default (index 0) above, except 32-bit keys without values from 2^26
+// of 8192 elements (1024 x 8) up to 2^21 elements (all sizes for 64-bit
+// pairs, as 512 x 8 up to 2^19): a small sort has few tiles, and a tile's
+// latency, not HBM, sets the pass time; the list's default (index 0)
+// above, except 32-bit keys without values from 2^26
 // keys on: tiles of 1024 x 24 (a pass 6.7% faster at 2^26, 3% slower at
 // 2^25, where fewer tiles are in flight).  Looked up by shape, so a
 // different list falls back to index 0.
@@ -180,12 +180,10 @@ static int default_index(int key_bytes, bool has_values, bool segmented, int c)
         return 0;
     int threads = 0, items = 0;
     if (key_bytes == 8 && has_values) {
-        if (c <= 17)
+        if (c <= 19)
             threads = 512, items = 8;
         else
             threads = 1024, items = 8;
-    } else if (c <= 15 && (has_values || key_bytes == 8)) {
-        threads = 256, items = 16;
     } else if (c <= 21) {
         threads = 1024, items = 8;
     } else if (key_bytes == 4 && !has_values && c >= 26) {

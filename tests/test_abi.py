@@ -177,14 +177,18 @@ def test_tune_table(rs, ctx):
     assert ctx.tune_get(32, True, True, 17) == 0
     ctx.tune_set(32, True, False, 26, -1)
     # built-in choices of unset plain-sort classes: 1024 x 8 tiles up to 2^21
-    # (from 2^18 up for 64-bit pairs), the list's default above (32-bit keys
-    # alone: 1024 x 24 from 2^26 on)
+    # (64-bit pairs: 512 x 8 up to 2^19, 1024 x 8 above), the list's default
+    # above (32-bit keys alone: 1024 x 24 from 2^26 on)
     for bits, pairs in ((32, False), (32, True), (64, False), (64, True)):
         c = rs.configs(bits, pairs)
         big = 39 if (bits, pairs) == (64, True) else 21
-        for cls in ((18, 25, big) if (bits, pairs) == (64, True) else (17, big)):
+        for cls in ((20, 25, big) if (bits, pairs) == (64, True) else (0, 15, 17, big)):
             i = ctx.tune_get(bits, pairs, False, cls)
             assert (c[i]["threads"], c[i]["items"], c[i]["radix_bits"]) == (1024, 8, 8), (bits, pairs, cls)
+        if (bits, pairs) == (64, True):
+            for cls in (15, 19):
+                i = ctx.tune_get(bits, pairs, False, cls)
+                assert (c[i]["threads"], c[i]["items"]) == (512, 8), cls
         if big < 39:
             assert ctx.tune_get(bits, pairs, False, big + 1) == 0
         if (bits, pairs) == (32, False):
