@@ -127,6 +127,16 @@ __device__ __forceinline__ void merge_chains(const K *s_k, uint32_t base, uint32
     }
 }
 
+// Orders this wave's LDS accesses before and after it: waits for the wave's
+// outstanding LDS operations and keeps the compiler from moving LDS
+// accesses across it (the lanes of one wave then see each other's writes).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Stable odd-even transposition sort of ITEMS registers: ITEMS rounds of
 // compare-exchanges between neighbours, exchanging only strictly greater
 // keys, so equal keys never pass each other.
@@ -217,15 +227,27 @@ __global__ __launch_bounds__(THREADS) void k_merge_tile(MergeTileArgs a)
     register_sort<K, V, HAS_V, ITEMS>(key, val);
 
     // merge runs of w elements pairwise in LDS, w = ITEMS, 2 ITEMS, ...
+    // While a pair of runs (2w elements) lies within one wave's kWave x ITEMS
+    // elements, a round reads only what its own wave wrote: a wave-level
+    // fence orders it (LDS accesses of one wave complete in order once the
+    // compiler waits for them); larger rounds need the workgroup barrier.
+    constexpr uint32_t kWaveSpan = kWave * ITEMS;
     for (uint32_t w = ITEMS; w < T; w *= 2) {
-        __syncthreads();  // every read of the previous round is done
+        const bool in_wave = 2 * w <= kWaveSpan;
+        if (in_wave)
+            wave_lds_fence();
+        else
+            __syncthreads();  // every read of the previous round is done
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             s_k[lds_slot<ITEMS>(t * ITEMS + j)] = key[j];
             if constexpr (HAS_V)
                 s_v[lds_slot<ITEMS>(t * ITEMS + j)] = val[j];
         }
-        __syncthreads();
+        if (in_wave)
+            wave_lds_fence();
+        else
+            __syncthreads();
         const uint32_t o = t * ITEMS;          // first output of this thread
         const uint32_t pb = o & ~(2 * w - 1);  // its pair of runs
         uint32_t src[ITEMS];
