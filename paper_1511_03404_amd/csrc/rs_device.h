@@ -262,11 +262,14 @@ template <int R, typename K, int ITEMS>
 __device__ __forceinline__ void wave_rank(const K (&key)[ITEMS], int shift, uint32_t *wc,
                                           uint64_t *wm, uint32_t lane, uint32_t (&rank)[ITEMS])
 {
-    const uint64_t lane_bit = 1ull << lane;
+    // the lane's bit lives in one 32-bit half of the 64-bit mask: OR only
+    // that half (half the LDS bytes of a 64-bit OR, the same mask)
+    const uint32_t lane_bit = 1u << (lane & 31);
+    uint32_t *wm32 = (uint32_t *)wm + (lane >> 5);
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t d = digit_of<R>(key[j], shift);
-        atomicOr(&wm[d], lane_bit);
+        atomicOr(&wm32[2 * d], lane_bit);
         const uint64_t m = wm[d];
         const uint32_t c = wc[d];
         const uint32_t below = lanes_below(m);
