@@ -103,6 +103,8 @@ struct HistArgs {
     uint4 *status;        // look-back words of all passes, cleared here
     uint64_t status_vec;  // number of uint4 in status
     uint32_t kmap;        // key order (kMap*), applied to every key read
+    uint32_t fine;        // small sorts: up to 16 keys per thread, key by key,
+                          // instead of batches (n <= 16 * grid * kHistThreads)
 };
 
 // Counters of k_hist: per digit position and per bin, kHistCols columns of
@@ -189,6 +191,31 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a)
     __syncthreads();
 
     const K *keys = (const K *)a.keys;
+    if (a.fine) {
+        // all of the thread's loads in flight before its first count
+        constexpr int FK = 16;
+        K key[FK];
+#pragma unroll
+        for (int j = 0; j < FK; ++j) {
+            const uint64_t idx = gtid + (uint64_t)j * gstride;
+            key[j] = idx < a.n ? keys[idx] : (K)0;
+        }
+#pragma unroll
+        for (int j = 0; j < FK; ++j) {
+            if (gtid + (uint64_t)j * gstride < a.n) {
+                const K k = map_in(key[j], a.kmap);
+#pragma unroll
+                for (int p = 0; p < D; ++p)
+                    hist_add<R, COLS>(tab, p, digit_of<R>(k, p * R), col);
+            }
+        }
+        __syncthreads();
+        if (a.part)
+            hist_store<D, R, COLS>(tab, a.part + (uint64_t)blockIdx.x * ((uint32_t)D << R), t);
+        else
+            hist_flush<D, R, COLS>(tab, a.hist, t);
+        return;
+    }
     const uint4 *vec = (const uint4 *)(keys + a.head);
     const uint64_t full_batches = a.nvec / BATCH;
     for (uint64_t b = blockIdx.x; b < full_batches; b += gridDim.x) {

@@ -275,6 +275,7 @@ struct Layout {
     uint64_t tiles;
     uint64_t off_ctrl, off_hist, off_base, off_part, off_status, off_tmp_k, off_tmp_v, total;
     uint32_t hist_blocks;   // workgroups of k_hist
+    bool hist_fine;         // k_hist counts key by key (small sorts), not in batches
     uint32_t parts;         // hist_blocks if k_hist writes row blocks, else 0
     uint64_t status_bytes;  // look-back words, claim counters, group aggregates of all passes
     uint64_t claim_words;
@@ -295,7 +296,15 @@ static Layout make_layout(int key_bytes, bool has_values, uint64_t n, const Sort
     o = align_up(o + (uint64_t)L.d * L.bins * 4, 256);
     L.off_base = o;
     o = align_up(o + (uint64_t)L.d * L.bins * 4, 256);
-    L.hist_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(512, (n + 16383) / 16384));
+    // k_hist: batches of 16384 keys per workgroup; up to 2^16 keys, one
+    // workgroup per 4096 keys, 4 per thread (a small sort's histogram then
+    // takes one short count, not one full batch: 1-3% of a 2^15-2^16 sort;
+    // with 8-16 keys per thread it is slower than the batches)
+    L.hist_fine = n <= 65536;
+    L.hist_blocks = L.hist_fine
+                        ? (uint32_t)std::max<uint64_t>(
+                              1, std::min<uint64_t>(kHistPartsMax, (n + 4095) / 4096))
+                        : (uint32_t)std::min<uint64_t>(512, (n + 16383) / 16384);
     L.parts = L.hist_blocks <= kHistPartsMax ? L.hist_blocks : 0u;
     L.off_part = o;
     o = align_up(o + (uint64_t)L.parts * L.d * L.bins * 4, 256);
@@ -566,6 +575,7 @@ static rs_status run_sort(rs_context *ctx, const K *kin, const K *vin, K *kout, 
     ha.status_vec = L.status_bytes / 16;
     uint32_t *part = (uint32_t *)(wb + L.off_part);
     ha.part = L.parts ? part : nullptr;
+    ha.fine = L.hist_fine ? 1u : 0u;
     launch(ctx, s, sizeof(K) == 4 ? "k_hist_u32" : "k_hist_u64",
            [&] { op.hist(ha, L.hist_blocks, s); });
 
