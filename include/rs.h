@@ -353,7 +353,10 @@ rs_status rs_tune_get(const rs_context *ctx, rs_key_type key_type, int has_value
  * stall bit 1 makes every look-back, bit 2 every tile claim after the
  * first, treat its predecessor as not yet published, so that each such wait
  * reaches its bound and the give-up path runs with every kernel still
- * exiting normally.  Applies to later calls on the context.
+ * exiting normally.  Only grouped claims wait: passes of more than 1024
+ * tiles (not 32-bit keys without values) and the segmented sort; a smaller
+ * pass claims its tiles from one counter without waiting.  Applies to later
+ * calls on the context.
  * spin_limit 0 or unknown stall bits -> RS_ERR_INVALID_ARGUMENT.
  *
  * rs_debug_sort_stages: the plain radix sort's kernels stage by stage, for
