@@ -204,6 +204,44 @@ def test_caller_workspace_and_streams(rs, oracle_lib):
             assert np.array_equal(host(ko), ok) and np.array_equal(host(vo), ov)
 
 
+def test_concurrent_sorts_on_streams(rs, oracle_lib):
+    """Sorts of several kinds and sizes enqueued on four streams with no
+    synchronisation between them run on the device at the same time: passes
+    that claim tiles in arrival order (up to 1024 tiles, and 32-bit keys
+    alone at any size) beside passes that claim them in XCD groups (1025
+    tiles), each with its own workspace.  Every result equals the oracle's
+    and every workspace reports no device error."""
+    cases = [(32, False, 1 << 17), (32, True, 1 << 20), (64, False, 1 << 19),
+             (32, True, 1024 * TILE + 5), (32, False, 1 << 25), (64, True, 1 << 18),
+             (32, True, 3 * TILE + 1), (64, False, (1 << 21) + 77)]
+    ctx = rs.context(0)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    jobs = []
+    for i, (bits, pairs, n) in enumerate(cases):
+        keys = datagen.keys("uniform", n, bits, seed=100 + i)
+        vals = datagen.values(n, bits) if pairs else None
+        kd = dev(keys)
+        vd = dev(vals) if pairs else None
+        ws = torch.empty(ctx.workspace_bytes(bits, pairs, n), dtype=torch.uint8, device="cuda")
+        jobs.append((bits, pairs, n, keys, vals, kd, vd, ws))
+    torch.cuda.synchronize()
+    outs = []
+    for i, (bits, pairs, n, keys, vals, kd, vd, ws) in enumerate(jobs):
+        print(f"case stream={i % 4} bits={bits} pairs={pairs} n={n}", flush=True)
+        with torch.cuda.stream(streams[i % 4]):
+            if pairs:
+                outs.append(rs.sort_pairs(kd, vd, workspace=ws))
+            else:
+                outs.append((rs.sort_keys(kd, workspace=ws), None))
+    torch.cuda.synchronize()
+    for (bits, pairs, n, keys, vals, kd, vd, ws), (ko, vo) in zip(jobs, outs):
+        assert ctx.status(ws) == rs.RS_OK, (bits, pairs, n)
+        ok, ov = oracle_lib.sort(keys, vals)
+        assert np.array_equal(host(ko), ok), (bits, pairs, n)
+        if pairs:
+            assert np.array_equal(host(vo), ov), (bits, pairs, n)
+
+
 @pytest.mark.parametrize("n", [3000, 3 * TILE + 5])
 @pytest.mark.parametrize("bits", [32, 64])
 @pytest.mark.parametrize("mask_bits", [0, 8, 16, 24, None])
