@@ -14,7 +14,9 @@ The model keeps what decides progress and drops the arithmetic:
     (its aggregate is published when its holder ranks it; inclusive values
     follow by induction);
   * only workgroups that are resident make claims, and only some of each
-    XCD's workgroups may be resident (other kernels hold the rest).
+    XCD's workgroups may be resident (other kernels hold the rest);
+  * flat = True is the arrival-order claim of passes of few tiles: one
+    global counter, no groups.
 Every atomic step is its own scheduling point, so an opener can be delayed
 between its two atomics.  The race between openers of one XCD is what the
 ordered opening (an opener takes its global id only after the XCD's previous
@@ -28,8 +30,9 @@ NO_TILE = -1
 
 
 class Model:
-    def __init__(self, xcds, wgs_per_xcd, tiles, group, ordered, seed, ahead=2):
+    def __init__(self, xcds, wgs_per_xcd, tiles, group, ordered, seed, ahead=2, flat=False):
         self.rng = random.Random(seed)
+        self.flat = flat   # one global counter, tiles in arrival order (no groups)
         self.G = group
         self.tiles = tiles
         self.ngroups = (tiles + group - 1) // group
@@ -50,6 +53,10 @@ class Model:
     def claim_step(self, wg):
         c = wg["claim"]
         x = wg["x"]
+        if self.flat:
+            t = self.ctr
+            self.ctr += 1
+            return t if t < self.tiles else NO_TILE
         if c["phase"] == "count":
             k = self.claims[x]
             self.claims[x] += 1
@@ -160,6 +167,15 @@ SHAPES = [
 @pytest.mark.parametrize("shape", SHAPES)
 def test_ordered_opening_processes_every_tile(shape, ahead):
     r = explore(True, range(200), ahead=ahead, **shape)
+    assert r == {"ok": 200, "deadlock": 0, "timeout": 0, "lost": 0}, r
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_flat_claims_process_every_tile(shape):
+    """Passes of few tiles (and 32-bit keys alone) claim from one global
+    counter in arrival order: every claimed tile is held by a running
+    workgroup, so every tile is processed under any schedule."""
+    r = explore(True, range(200), ahead=0, flat=True, **shape)
     assert r == {"ok": 200, "deadlock": 0, "timeout": 0, "lost": 0}, r
 
 
