@@ -65,10 +65,11 @@ def test_histograms_and_each_pass(rs, oracle_lib, bits, pairs, index, dist):
 
 
 @pytest.mark.parametrize("dist", ["uniform", "bucket"])
-@pytest.mark.parametrize("n", [16 * 16384, 16 * 16384 + 1])
+@pytest.mark.parametrize("n", [1 << 16, (1 << 16) + 1, 16 * 16384, 16 * 16384 + 1])
 @pytest.mark.parametrize("bits,pairs", KINDS)
 def test_histogram_modes(rs, oracle_lib, bits, pairs, n, dist):
-    """Both ways of building the histograms: up to 16 histogram workgroups
+    """Every way of building the histograms: up to 2^16 keys one workgroup
+    per 4096 keys counting them key by key; up to 16 histogram workgroups
     (one per 16384 keys) each write a row block that the plan kernel sums;
     from 17 on they add into one cleared histogram.  Either way the
     histograms and every pass equal the oracle's."""

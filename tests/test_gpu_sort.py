@@ -204,6 +204,18 @@ def test_caller_workspace_and_streams(rs, oracle_lib):
             assert np.array_equal(host(ko), ok) and np.array_equal(host(vo), ov)
 
 
+@pytest.mark.parametrize("n", [1024 * TILE, 1024 * TILE + 1])
+def test_claim_modes_at_the_limit(rs, oracle_lib, n):
+    """32-bit pairs in 1024 tiles (claimed in arrival order) and in 1025
+    (claimed in XCD groups): both equal the oracle."""
+    print(f"case u32 pairs n={n}", flush=True)
+    keys = datagen.keys("uniform", n, 32, seed=7)
+    vals = datagen.values(n, 32)
+    gk, gv = gpu_sort(rs, keys, vals)
+    ok, ov = oracle_lib.sort(keys, vals)
+    assert np.array_equal(gk, ok) and np.array_equal(gv, ov)
+
+
 def test_concurrent_sorts_on_streams(rs, oracle_lib):
     """Sorts of several kinds and sizes enqueued on four streams with no
     synchronisation between them run on the device at the same time: passes
