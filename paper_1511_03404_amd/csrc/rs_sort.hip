@@ -169,11 +169,11 @@ static const SegOps *seg_table(int key_bytes, bool has_values, int *count)
 // the autotuner selected on MI355X for plain sorts of uniform keys.  Tiles
 // of 8192 elements (1024 x 8) up to 2^21 elements (all sizes for 64-bit
 // pairs, as 512 x 8 up to 2^19): a small sort has few tiles, and a tile's
-// latency, not HBM, sets the pass time; the list's default (index 0)
-// above, except 32-bit keys without values from 2^26
-// keys on: tiles of 1024 x 24 (a pass 6.7% faster at 2^26, 3% slower at
-// 2^25, where fewer tiles are in flight).  Looked up by shape, so a
-// different list falls back to index 0.
+// latency, not HBM, sets the pass time.  Above, the list's default (index
+// 0), except 32-bit keys without values from 2^26 keys on: tiles of
+// 1024 x 24 (a pass 6.7% faster at 2^26, 3% slower at 2^25, where fewer
+// tiles are in flight).  Looked up by shape, so a different list falls
+// back to index 0.
 static int default_index(int key_bytes, bool has_values, bool segmented, int c)
 {
     if (segmented)
