@@ -91,6 +91,23 @@ def test_orders_match_oracle(rs, oracle_lib, bits, pairs, order, desc):
                 assert np.array_equal(gv, ov), f"values differ n={n} {dist}"
 
 
+@pytest.mark.parametrize("order,desc", [("signed", True), ("float", False)])
+@pytest.mark.parametrize("bits,pairs,tile", [(32, True, TILE), (64, False, TILE),
+                                             (64, True, TILE // 2)])
+def test_orders_with_grouped_claims(rs, oracle_lib, bits, pairs, tile, order, desc):
+    """Sorts of 1025 tiles claim them in XCD groups (smaller ones in arrival
+    order): the maps of the first and last pass on that path too."""
+    n = 1024 * tile + 1
+    print(f"case bits={bits} pairs={pairs} order={order} desc={desc} n={n}", flush=True)
+    keys = order_keys("gaussian", n, bits, 11, order)
+    vals = datagen.values(n, bits) if pairs else None
+    ok, ov = oracle_lib.sort_ordered(keys, vals, order, desc)
+    gk, gv = run_sort(rs, keys, vals, order, desc)
+    assert np.array_equal(gk, ok)
+    if pairs:
+        assert np.array_equal(gv, ov)
+
+
 @pytest.mark.parametrize("order,desc", ORDERS)
 @pytest.mark.parametrize("bits,pairs", KINDS)
 def test_orders_in_place_and_skipped_passes(rs, oracle_lib, bits, pairs, order, desc):
