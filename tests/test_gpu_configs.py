@@ -92,6 +92,23 @@ def test_every_config_matches_oracle(rs, oracle_lib, bits, pairs, index):
 
 
 @pytest.mark.parametrize("bits,pairs,index", CASES)
+def test_every_config_grouped_claims(rs, oracle_lib, bits, pairs, index):
+    """1025 tiles: passes claim them in XCD groups (except 32-bit keys
+    alone, which always claim in arrival order), for every configuration."""
+    ctx, cfg = config_ctx(rs, bits, pairs, index)
+    n = 1025 * cfg["threads"] * cfg["items"] - 7
+    print(f"case grouped bits={bits} pairs={pairs} cfg={cfg} n={n}", flush=True)
+    keys = datagen.keys("uniform", n, bits, seed=index + 5)
+    vals = datagen.values(n, bits) if pairs else None
+    ok, ov = oracle_lib.sort(keys, vals)
+    gk, gv = sort(rs, ctx, keys, vals)
+    assert np.array_equal(gk, ok), f"keys differ: {cfg} n={n}"
+    if pairs:
+        assert np.array_equal(gv, ov), f"values differ: {cfg} n={n}"
+    ctx.close()
+
+
+@pytest.mark.parametrize("bits,pairs,index", CASES)
 def test_every_config_in_place(rs, oracle_lib, bits, pairs, index):
     """In place, with every pass moving data and with the low digits all
     equal (skipped passes change the parity of the moving ones)."""
