@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -886,6 +887,17 @@ def measure_copy(torch, dev, nbytes=1 << 30, reps=20):
                    "(rs_device_copy) and torch copy_ (the runtime's); the faster one"}
 
 
+def moving_passes(keys, bits, r=8):
+    """Digit positions (r bits) at which the keys are not all equal: the
+    passes of an LSD sort that move data (an all-equal digit is the identity
+    permutation and its pass is skipped)."""
+    import numpy as np
+    u = keys.view(np.uint32 if bits == 32 else np.uint64)
+    diff = np.bitwise_or.reduce(u ^ u[0]) if u.size else 0
+    mask = (1 << r) - 1
+    return sum(1 for p in range(bits // r) if (int(diff) >> (p * r)) & mask)
+
+
 def measure_sorts(args, torch, rs, datagen, dev, workload, steps, warmup, with_cpu=True):
     """One radix-sort workload: one sort per distribution per step, inputs
     resident in HBM, out of place; the dict of the JSON line."""
@@ -894,10 +906,16 @@ def measure_sorts(args, torch, rs, datagen, dev, workload, steps, warmup, with_c
     kb = bits // 8
     vb = kb if has_v else 0
 
-    # inputs resident in HBM before timing
+    # inputs resident in HBM before timing; per input, how many digit
+    # positions (8-bit) are not the same for every key: the passes that move
+    # data (the others are skipped)
     ins = []
+    moving = {}
     for d in dists:
-        k = torch.from_numpy(datagen.keys(d, n, bits, seed=1)).to(dev)
+        kh = datagen.keys(d, n, bits, seed=1)
+        moving[d] = moving_passes(kh, bits)
+        k = torch.from_numpy(kh).to(dev)
+        del kh
         v = torch.from_numpy(datagen.values(n, bits)).to(dev) if has_v else None
         ins.append((d, k, v))
     ko = torch.empty(n, dtype=ins[0][1].dtype, device=dev)
@@ -945,12 +963,21 @@ def measure_sorts(args, torch, rs, datagen, dev, workload, steps, warmup, with_c
     # per-distribution times from the events (sum of the kernels of one sort)
     per = {}
     for i, d in enumerate(dists):
-        tot = sum(ms for name, tag, ms in recs if tag == i)
-        sort_ms = tot / steps
+        mine = [ms for name, tag, ms in recs if tag == i]
+        sort_ms = sum(mine) / steps
+        # the launches of one sort are consecutive: per-sort times, median
+        per_launch = len(mine) // steps
+        sorts = [sum(mine[j * per_launch:(j + 1) * per_launch]) for j in range(steps)]
         b_alg = kb * 2 * n * (kb + vb)  # P8 passes x 2 x n x (k + v)
+        # bytes the executed passes move (a copy when every pass is skipped)
+        b_exec = max(moving[d], 1) * 2 * n * (kb + vb)
         per[d] = {"ms_per_sort": round(sort_ms, 4),
+                  "ms_per_sort_median": round(statistics.median(sorts), 4),
                   "Mkeys_s": round(n / sort_ms / 1e3, 1),
-                  "hbm_frac_alg": round(b_alg / (sort_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+                  "hbm_frac_alg": round(b_alg / (sort_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                  "passes_moving": moving[d],
+                  "bytes_executed": b_exec,
+                  "hbm_frac_executed": round(b_exec / (sort_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
         kern = {}
         for name, tag, ms in recs:
             if tag == i:
@@ -967,9 +994,12 @@ def measure_sorts(args, torch, rs, datagen, dev, workload, steps, warmup, with_c
         avg = sum(pass_ms) / len(pass_ms)
         bytes_per_launch = 2 * n * (kb + vb)  # read + write of keys and values, one digit
         achieved = bytes_per_launch / (avg * 1e-3) / 1e9
+        traffic = measured_traffic(workload, cfg)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(workload, cfg),
+                    "traffic": traffic,
+                    # the counters' bytes over the same launch time (null without them)
+                    "traffic_GBs": (round(traffic / (avg * 1e-3) / 1e9, 1) if traffic else None),
                     "kernel": pass_name, "kernel_instance": pass_kernel_name(bits, has_v, cfg),
                     "avg_launch_ms": round(avg, 5),
                     "launches": len(pass_ms), "bytes_per_launch": bytes_per_launch,
